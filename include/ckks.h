@@ -1,0 +1,202 @@
+/*
+ * ckks.h - C-ABI of the gfx950 (MI355X) RNS-CKKS key-switching library.
+ *
+ * The library computes the hot path of homomorphic multiplication and
+ * rotation with hybrid key-switching over RNS polynomials in exact 32-bit
+ * word arithmetic: negacyclic NTT / INTT, automorphism, ModUp / ModDown base
+ * conversion, the evaluation-key inner product, tensoring and rescale
+ * (paper: Sec. II-A/II-B for the data and the polynomial operations, Fig.
+ * keysw and Sec. IV for the three key-switching stages).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value: 0 (CKKS_OK) or a negative CKKS_E* code.  On error nothing has
+ *   been enqueued and ckks_last_error() (thread-local) describes the cause.
+ *   No C++ exception crosses this boundary.
+ * Pointers: every data pointer is a DEVICE pointer on the context's device,
+ *   4-byte aligned (256-byte alignment is recommended), owned by the caller.
+ *   The library never frees or retains them past the call.  Host pointers are
+ *   named h_* and are read before the call returns.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *   stream).  Calls are asynchronous: they enqueue kernels and return.  A
+ *   device fault surfaces at the caller's next synchronisation.
+ * Residues: uint32, canonical in [0, q), normal (not Montgomery) form.
+ *   Inputs outside [0, q) give unspecified (but in-bounds) results.
+ * Layout: limb-major.  A polynomial at level L is [L][N] (row i modulo q_i),
+ *   with the special-prime rows p_0..p_{k-1} appended when "with P"; a
+ *   ciphertext is [2][L][N] = (c0, c1), decrypting to c0 + c1 * s.
+ *   Evaluation domain = bit-reversed NTT order A[j] = a(psi^(2 brv(j) + 1)),
+ *   psi the smallest primitive 2N-th root of unity modulo the row's prime.
+ * Keys: a key-switching key is [beta_max][2][L_max + k][N] in the evaluation
+ *   domain, beta_max = ceil(L_max / alpha), alpha = k; at level L the rows
+ *   [0, L) and [L_max, L_max + k) are used.  Component 0 is b, 1 is a.
+ * Digits: digit j of a level-L polynomial is Q-rows [j*alpha, min((j+1)*alpha, L)).
+ * Workspace: operations that need scratch take (ws, ws_bytes), a device
+ *   buffer of at least ckks_workspace_bytes(ctx, op, L) bytes owned by the
+ *   caller; nothing is allocated inside an operation.  One workspace must
+ *   not be used by two calls that may run concurrently.
+ * Aliasing: ckks_ntt / ckks_intt are in place.  Elsewhere an output must not
+ *   overlap any input unless stated.
+ * Thread safety: a context is immutable after creation; calls on different
+ *   streams with different workspaces may run concurrently.
+ */
+#ifndef CKKS_H
+#define CKKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CKKS_OK = 0,
+    CKKS_EINVAL = -1,       /* bad argument (null pointer, level out of range, ...) */
+    CKKS_ENOMEM = -2,       /* workspace too small, or device allocation failed */
+    CKKS_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+    CKKS_EUNSUPPORTED = -4  /* parameters outside what the kernels support */
+};
+
+/* Operation ids for ckks_workspace_bytes. */
+enum {
+    CKKS_OP_NTT = 0,
+    CKKS_OP_MODUP = 1,
+    CKKS_OP_MODDOWN = 2,
+    CKKS_OP_KEYSWITCH = 3,
+    CKKS_OP_HMULT = 4,
+    CKKS_OP_HROT = 5,
+    CKKS_OP_RESCALE = 6,
+    CKKS_OP_HROT_HOISTED = 7
+};
+
+typedef struct ckks_ctx ckks_ctx;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *ckks_last_error(void);
+
+/*
+ * Create a context for ring degree N = 2^logN (12 <= logN <= 16) over the
+ * chain h_q[0..L_max) and special primes h_p[0..k) (host arrays), on HIP
+ * device `device`.  Every prime must be < 2^30, prime, 1 mod 2N and
+ * distinct; dnum gives the digit size alpha = ceil(L_max / dnum), which must
+ * equal k (Sec. IV-A: alpha special primes per digit).  The context builds
+ * its twiddle tables (Sec. II-B1), the BConv tables T[i][j] = (Q^* / Q_j)
+ * mod P_i with Q^* the product of the input moduli (Sec. III-C2) for every
+ * level and digit, and checks the overflow-free condition
+ * sum_j T[i][j] * Q_j < 2^64 of Sec. III-C2 for every table.
+ * Errors: CKKS_EINVAL (bad primes / sizes), CKKS_EUNSUPPORTED (logN or
+ * L_max + k out of range, bound violated), CKKS_ENOMEM, CKKS_EHIP.
+ * Owns device memory until ckks_ctx_destroy.
+ */
+int ckks_ctx_create(ckks_ctx **out, int logN, const uint32_t *h_q, int L_max,
+                    const uint32_t *h_p, int k, int dnum, int device);
+int ckks_ctx_destroy(ckks_ctx *ctx);
+
+/* Device bytes of workspace needed by operation `op` (CKKS_OP_*) at level L;
+ * for CKKS_OP_HROT_HOISTED, per call (independent of the rotation count). */
+size_t ckks_workspace_bytes(const ckks_ctx *ctx, int op, int L);
+
+/*
+ * Forward / inverse negacyclic NTT in place (Sec. II-B1: (N/2) log2 N
+ * butterflies per limb, Cooley-Tukey forward, Gentleman-Sande inverse).
+ * a: [L (+k if with_P)][N]; row i is modulo q_i, appended rows modulo p_m.
+ * Forward maps natural coefficients to the bit-reversed evaluation domain;
+ * the inverse includes the N^-1 scale.  1 <= L <= L_max.
+ */
+int ckks_ntt(const ckks_ctx *ctx, uint32_t *a, int L, int with_P, void *stream);
+int ckks_intt(const ckks_ctx *ctx, uint32_t *a, int L, int with_P, void *stream);
+
+/*
+ * Automorphism sigma_g, g = 5^rot mod 2N, on evaluation-domain rows (Sec.
+ * II-B3: a column permutation, the same for every limb):
+ * out[r][j] = in[r][j'] with 2 brv(j') + 1 = g (2 brv(j) + 1) mod 2N.
+ * in/out: [rows][N]; rows is any positive row count.  out must not alias in.
+ */
+int ckks_automorph(const ckks_ctx *ctx, const uint32_t *in, uint32_t *out, int rows, int rot,
+                   void *stream);
+
+/*
+ * Tensoring (Sec. II-B3, element-wise): ct1, ct2 [2][L][N] -> out [3][L][N],
+ * d0 = c0 c0', d1 = c0 c1' + c1 c0', d2 = c1 c1' (mod q_i).
+ */
+int ckks_tensor(const ckks_ctx *ctx, const uint32_t *ct1, const uint32_t *ct2, int L,
+                uint32_t *out, void *stream);
+
+/*
+ * ModUp, key-switching stage 1 (Fig. keysw, Sec. IV-A), for every digit j:
+ * INTT of the digit's limbs, fast BConv (Sec. II-B2, III-C2) from D_j to the
+ * other moduli of Q_L and P, NTT of the new limbs; the digit's own rows are
+ * copied.  d: [L][N] evaluation domain.  out: [beta][L + k][N],
+ * beta = ceil(L / alpha), rows q_0..q_{L-1}, p_0..p_{k-1}.
+ */
+int ckks_modup(const ckks_ctx *ctx, const uint32_t *d, int L, uint32_t *out, void *ws,
+               size_t ws_bytes, void *stream);
+
+/*
+ * Evaluation-key inner product, key-switching stage 2 (Sec. IV-B):
+ * acc[c][r] = sum_{j < beta} M[j][r] * evk[j][c][row(r)] for c = 0, 1,
+ * row(r) = r for r < L, L_max + (r - L) otherwise.
+ * M: [beta][L + k][N]; evk: key layout; acc: [2][L + k][N].
+ */
+int ckks_inner_product(const ckks_ctx *ctx, const uint32_t *M, int L, const uint32_t *evk,
+                       uint32_t *acc, void *stream);
+
+/*
+ * ModDown, key-switching stage 3 (Fig. keysw): out = (a_Q - NTT(BConv_{P->Q}
+ * (INTT(a_P)))) * P^-1 mod q_i, floor form (no rounding offset).
+ * in: [L + k][N] evaluation domain; out: [L][N].
+ */
+int ckks_moddown(const ckks_ctx *ctx, const uint32_t *in, int L, uint32_t *out, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/*
+ * Key-switching (Fig. keysw): out[c] = ModDown(sum_j ModUp_j(d) * evk[j][c]).
+ * d: [L][N] evaluation domain; evk: key layout; out: [2][L][N].
+ */
+int ckks_keyswitch(const ckks_ctx *ctx, const uint32_t *d, int L, const uint32_t *evk,
+                   uint32_t *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * HMult with relinearisation, no rescale (Sec. II-A; key-switching of the
+ * s^2 term): out = (d0 + KS_0(d2), d1 + KS_1(d2)) with (d0, d1, d2) the
+ * tensor of ct1 and ct2.  ct1, ct2, out: [2][L][N]; rlk: key for s^2 -> s.
+ * out may alias neither input.
+ */
+int ckks_hmult(const ckks_ctx *ctx, const uint32_t *ct1, const uint32_t *ct2, int L,
+               const uint32_t *rlk, uint32_t *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * HRot by `rot` slots (left), g = 5^rot mod 2N: out = (sigma(c0) +
+ * KS_0(sigma(c1)), KS_1(sigma(c1))).  rotk must switch sigma_g(s) -> s; the
+ * library cannot check that.  ct, out: [2][L][N].
+ */
+int ckks_hrot(const ckks_ctx *ctx, const uint32_t *ct, int L, int rot, const uint32_t *rotk,
+              uint32_t *out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Hoisted rotations (rotations reordered so that one ModUp is shared;
+ * Sec. V-C): M = ModUp(c1) once; for each n: sigma_{g_n} on every row of M
+ * (Q and P), inner product with h_rotks[n], ModDown, plus sigma_{g_n}(c0).
+ * Not bitwise equal to n separate ckks_hrot calls (the base conversion is
+ * not permutation-equivariant), but decrypts to the same rotations.
+ * h_rots, h_rotks, h_outs: host arrays of n entries (keys and outputs are
+ * device pointers).  n >= 1.
+ */
+int ckks_hrot_hoisted(const ckks_ctx *ctx, const uint32_t *ct, int L, const int *h_rots, int n,
+                      const uint32_t *const *h_rotks, uint32_t *const *h_outs, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/*
+ * Rescale by the top prime (drop q_{L-1}): for each component,
+ * t = INTT_{q_{L-1}}(a_{L-1}); out_i = (a_i - NTT_{q_i}(t mod q_i)) * q_{L-1}^-1,
+ * floor form.  ct: [2][L][N] -> out: [2][L-1][N]; L >= 2.
+ */
+int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, void *ws,
+                 size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CKKS_H */

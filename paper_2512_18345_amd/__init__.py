@@ -1,0 +1,221 @@
+"""Python binding of libckks.so, the gfx950 RNS-CKKS key-switching library.
+
+Argument marshalling only: every function below forwards to the C entry
+point of the same name (declared in include/ckks.h); all arithmetic runs in
+the library's HIP kernels.  Tensors are device tensors (torch, any 32-bit
+integer dtype, contiguous); PyTorch supplies device memory and streams.
+There is no fallback: if the library is not built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+__all__ = [
+    "CkksError", "lib", "Context", "OP",
+    "ckks_ctx_create", "ckks_ctx_destroy", "ckks_workspace_bytes",
+    "ckks_ntt", "ckks_intt", "ckks_automorph", "ckks_tensor", "ckks_modup",
+    "ckks_inner_product", "ckks_moddown", "ckks_keyswitch", "ckks_hmult",
+    "ckks_hrot", "ckks_hrot_hoisted", "ckks_rescale",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libckks.so")
+
+OP = dict(NTT=0, MODUP=1, MODDOWN=2, KEYSWITCH=3, HMULT=4, HROT=5, RESCALE=6, HROT_HOISTED=7)
+
+
+class CkksError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ckks error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_sz = ctypes.c_size_t
+
+_SIGS = {
+    "ckks_ctx_create": [ctypes.POINTER(_vp), _i, _vp, _i, _vp, _i, _i, _i],
+    "ckks_ctx_destroy": [_vp],
+    "ckks_ntt": [_vp, _vp, _i, _i, _vp],
+    "ckks_intt": [_vp, _vp, _i, _i, _vp],
+    "ckks_automorph": [_vp, _vp, _vp, _i, _i, _vp],
+    "ckks_tensor": [_vp, _vp, _vp, _i, _vp, _vp],
+    "ckks_modup": [_vp, _vp, _i, _vp, _vp, _sz, _vp],
+    "ckks_inner_product": [_vp, _vp, _i, _vp, _vp, _vp],
+    "ckks_moddown": [_vp, _vp, _i, _vp, _vp, _sz, _vp],
+    "ckks_keyswitch": [_vp, _vp, _i, _vp, _vp, _vp, _sz, _vp],
+    "ckks_hmult": [_vp, _vp, _vp, _i, _vp, _vp, _vp, _sz, _vp],
+    "ckks_hrot": [_vp, _vp, _i, _i, _vp, _vp, _vp, _sz, _vp],
+    "ckks_hrot_hoisted": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp],
+    "ckks_rescale": [_vp, _vp, _i, _vp, _vp, _sz, _vp],
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libckks.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2512_18345_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _i
+        L.ckks_last_error.restype = ctypes.c_char_p
+        L.ckks_last_error.argtypes = []
+        L.ckks_workspace_bytes.restype = _sz
+        L.ckks_workspace_bytes.argtypes = [_vp, _i, _i]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CkksError(rc, lib().ckks_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device address of a tensor (or an int address / None)."""
+    if t is None or isinstance(t, int):
+        return t
+    if t.dtype.itemsize != 4 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("expected a contiguous 32-bit integer device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ws(ws):
+    if ws is None:
+        return None, 0
+    return _ptr(ws), ws.numel() * ws.element_size()
+
+
+def _u32_array(vals: Sequence[int]):
+    arr = (ctypes.c_uint32 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+# ----- one wrapper per C entry point -----------------------------------------
+
+def ckks_ctx_create(logN: int, q: Sequence[int], p: Sequence[int], dnum: int, device: int = 0) -> int:
+    h = _vp()
+    qa, pa = _u32_array(q), _u32_array(p)
+    _check(lib().ckks_ctx_create(ctypes.byref(h), logN, ctypes.cast(qa, _vp), len(q),
+                                 ctypes.cast(pa, _vp), len(p), dnum, device))
+    return h.value
+
+
+def ckks_ctx_destroy(ctx: int) -> None:
+    _check(lib().ckks_ctx_destroy(ctx))
+
+
+def ckks_workspace_bytes(ctx: int, op: int, L: int) -> int:
+    return int(lib().ckks_workspace_bytes(ctx, op, L))
+
+
+def ckks_ntt(ctx, a, L, with_P=False, stream=None):
+    _check(lib().ckks_ntt(ctx, _ptr(a), L, int(bool(with_P)), _stream(stream)))
+
+
+def ckks_intt(ctx, a, L, with_P=False, stream=None):
+    _check(lib().ckks_intt(ctx, _ptr(a), L, int(bool(with_P)), _stream(stream)))
+
+
+def ckks_automorph(ctx, inp, out, rows, rot, stream=None):
+    _check(lib().ckks_automorph(ctx, _ptr(inp), _ptr(out), rows, rot, _stream(stream)))
+
+
+def ckks_tensor(ctx, ct1, ct2, L, out, stream=None):
+    _check(lib().ckks_tensor(ctx, _ptr(ct1), _ptr(ct2), L, _ptr(out), _stream(stream)))
+
+
+def ckks_modup(ctx, d, L, out, ws=None, stream=None):
+    w, nb = _ws(ws)
+    _check(lib().ckks_modup(ctx, _ptr(d), L, _ptr(out), w, nb, _stream(stream)))
+
+
+def ckks_inner_product(ctx, M, L, evk, acc, stream=None):
+    _check(lib().ckks_inner_product(ctx, _ptr(M), L, _ptr(evk), _ptr(acc), _stream(stream)))
+
+
+def ckks_moddown(ctx, inp, L, out, ws=None, stream=None):
+    w, nb = _ws(ws)
+    _check(lib().ckks_moddown(ctx, _ptr(inp), L, _ptr(out), w, nb, _stream(stream)))
+
+
+def ckks_keyswitch(ctx, d, L, evk, out, ws=None, stream=None):
+    w, nb = _ws(ws)
+    _check(lib().ckks_keyswitch(ctx, _ptr(d), L, _ptr(evk), _ptr(out), w, nb, _stream(stream)))
+
+
+def ckks_hmult(ctx, ct1, ct2, L, rlk, out, ws=None, stream=None):
+    w, nb = _ws(ws)
+    _check(lib().ckks_hmult(ctx, _ptr(ct1), _ptr(ct2), L, _ptr(rlk), _ptr(out), w, nb, _stream(stream)))
+
+
+def ckks_hrot(ctx, ct, L, rot, rotk, out, ws=None, stream=None):
+    w, nb = _ws(ws)
+    _check(lib().ckks_hrot(ctx, _ptr(ct), L, rot, _ptr(rotk), _ptr(out), w, nb, _stream(stream)))
+
+
+def ckks_hrot_hoisted(ctx, ct, L, rots, rotks, outs, ws=None, stream=None):
+    n = len(rots)
+    assert len(rotks) == n and len(outs) == n
+    r = (ctypes.c_int * n)(*[int(v) for v in rots])
+    k = (_vp * n)(*[_ptr(t) for t in rotks])
+    o = (_vp * n)(*[_ptr(t) for t in outs])
+    w, nb = _ws(ws)
+    _check(lib().ckks_hrot_hoisted(ctx, _ptr(ct), L, ctypes.cast(r, _vp), n, ctypes.cast(k, _vp),
+                                   ctypes.cast(o, _vp), w, nb, _stream(stream)))
+
+
+def ckks_rescale(ctx, ct, L, out, ws=None, stream=None):
+    w, nb = _ws(ws)
+    _check(lib().ckks_rescale(ctx, _ptr(ct), L, _ptr(out), w, nb, _stream(stream)))
+
+
+class Context:
+    """Owns a ckks_ctx for one ring degree; allocates workspaces with torch."""
+
+    def __init__(self, logN: int, q: Sequence[int], p: Sequence[int], dnum: int, device: int = 0):
+        self.logN, self.N = logN, 1 << logN
+        self.q, self.p, self.dnum, self.device = list(q), list(p), dnum, device
+        self.L_max, self.k = len(q), len(p)
+        self.alpha = -(-self.L_max // dnum)
+        self.handle = ckks_ctx_create(logN, q, p, dnum, device)
+
+    @classmethod
+    def from_spec(cls, spec, device: int = 0) -> "Context":
+        return cls(spec.logN, spec.q, spec.p, spec.dnum, device)
+
+    def beta(self, L: int) -> int:
+        return -(-L // self.alpha)
+
+    def workspace(self, op: str, L: int):
+        import torch
+        nb = ckks_workspace_bytes(self.handle, OP[op], L)
+        return torch.empty(max(nb // 4, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+
+    def close(self):
+        if self.handle:
+            ckks_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

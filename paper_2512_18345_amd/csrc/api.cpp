@@ -1,0 +1,426 @@
+// C-ABI entry points (include/ckks.h): argument checks, workspace layout and
+// the order of kernel launches for each operation.  Every step of every
+// operation runs in the gfx950 kernels of kernels.hip; this file only
+// validates and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ctx.h"
+#include "kernels.h"
+
+using namespace ckks;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(CKKS_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define CKKS_TRY(expr, where)                        \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's workspace.
+struct WS {
+  char* base;
+  size_t size, used = 0;
+  uint32_t* take(size_t words) {
+    uint32_t* p = reinterpret_cast<uint32_t*>(base + used);
+    used += round_up(words * 4);
+    return p;
+  }
+};
+
+size_t words(const Ctx& c, size_t rows) { return rows * (size_t)c.N; }
+
+size_t ws_modup(const Ctx& c, int L) { return round_up(words(c, L) * 4); }
+size_t ws_moddown(const Ctx& c, int L) { return round_up(words(c, c.k) * 4) + round_up(words(c, L) * 4); }
+size_t ws_keyswitch(const Ctx& c, int L) {
+  return ws_modup(c, L) + round_up(words(c, (size_t)c.beta(L) * (L + c.k)) * 4) +
+         round_up(words(c, 2 * (size_t)(L + c.k)) * 4) + ws_moddown(c, L);
+}
+size_t ws_bytes(const Ctx& c, int op, int L) {
+  switch (op) {
+    case CKKS_OP_NTT: return 0;
+    case CKKS_OP_MODUP: return ws_modup(c, L);
+    case CKKS_OP_MODDOWN: return ws_moddown(c, L);
+    case CKKS_OP_KEYSWITCH: return ws_keyswitch(c, L);
+    case CKKS_OP_HMULT: return round_up(words(c, 3 * (size_t)L) * 4) + ws_keyswitch(c, L);
+    case CKKS_OP_HROT: return round_up(words(c, 2 * (size_t)L) * 4) + ws_keyswitch(c, L);
+    case CKKS_OP_HROT_HOISTED:
+      return 2 * round_up(words(c, (size_t)c.beta(L) * (L + c.k)) * 4) + round_up(words(c, L) * 4) +
+             round_up(words(c, 2 * (size_t)(L + c.k)) * 4) + ws_modup(c, L) + ws_moddown(c, L);
+    case CKKS_OP_RESCALE: return round_up(words(c, 1) * 4) + round_up(words(c, L) * 4);
+    default: return 0;
+  }
+}
+
+int check_level(const ckks_ctx* ctx, int L, int lo = 1) {
+  if (!ctx) return fail(CKKS_EINVAL, "null context");
+  if (L < lo || L > ctx->c.L_max)
+    return fail(CKKS_EINVAL, "level L=" + std::to_string(L) + " outside [" + std::to_string(lo) +
+                                 ", " + std::to_string(ctx->c.L_max) + "]");
+  return CKKS_OK;
+}
+
+int check_ws(const Ctx& c, int op, int L, const void* ws, size_t ws_bytes_given) {
+  const size_t need = ws_bytes(c, op, L);
+  if (need && !ws) return fail(CKKS_EINVAL, "null workspace");
+  if (ws_bytes_given < need)
+    return fail(CKKS_ENOMEM, "workspace of " + std::to_string(ws_bytes_given) + " bytes < " +
+                                 std::to_string(need) + " needed");
+  return CKKS_OK;
+}
+
+uint32_t galois(const Ctx& c, int rot) {
+  const uint64_t two_n = 2ull * c.N;
+  const uint64_t half = (uint64_t)c.N / 2;
+  uint64_t e = ((int64_t)rot % (int64_t)half + (int64_t)half) % half;
+  uint64_t g = 1, b = 5;
+  while (e) {
+    if (e & 1) g = g * b % two_n;
+    b = b * b % two_n;
+    e >>= 1;
+  }
+  return (uint32_t)g;
+}
+
+// ---- compositions ---------------------------------------------------------
+
+// ModUp of d [L][N] into M [beta][L + k][N]; y: [L][N] scratch.
+int modup_impl(const Ctx& c, const uint32_t* d, int L, uint32_t* M, uint32_t* y, hipStream_t st) {
+  const size_t N = c.N;
+  const int R = L + c.k;
+  const RowMap rm = c.rows(L);
+  CKKS_TRY(launch_intt(c, d, y, L, rm, 0, 0, c.d_modup_scale + (size_t)L * c.L_max, 0, st),
+           "ModUp INTT");
+  for (int j = 0; j < c.beta(L); ++j) {
+    const int lo = j * c.alpha, hi = std::min(lo + c.alpha, L);
+    uint32_t* Mj = M + (size_t)j * R * N;
+    CKKS_TRY(launch_bconv(c, rm, y + lo * N, hi - lo, Mj, R, lo, hi,
+                          c.d_modup_T + c.modup_T_off[(size_t)L * c.beta_max() + j], c.alpha, st),
+             "ModUp BConv");
+    CKKS_TRY(hipMemcpyAsync(Mj + lo * N, d + lo * N, (size_t)(hi - lo) * N * 4,
+                            hipMemcpyDeviceToDevice, st),
+             "ModUp digit copy");
+    CKKS_TRY(launch_ntt(c, Mj, Mj, R, rm, lo, hi, st), "ModUp NTT");
+  }
+  return CKKS_OK;
+}
+
+// ModDown of a [L + k][N] into out [L][N] (+ add if non-null); x: [k][N], z: [L][N] scratch.
+int moddown_impl(const Ctx& c, const uint32_t* a, int L, const uint32_t* add, uint32_t* out,
+                 uint32_t* x, uint32_t* z, hipStream_t st) {
+  const size_t N = c.N;
+  CKKS_TRY(launch_intt(c, a + (size_t)L * N, x, c.k, RowMap{0, c.L_max}, 0, 0, c.d_moddown_scale,
+                       c.L_max, st),
+           "ModDown INTT");
+  CKKS_TRY(launch_bconv(c, c.rows(L), x, c.k, z, L, 0, 0, c.d_moddown_T, c.k, st), "ModDown BConv");
+  CKKS_TRY(launch_ntt(c, z, z, L, c.rows(L), 0, 0, st), "ModDown NTT");
+  CKKS_TRY(launch_moddown_combine(c, L, a, z, add, out, st), "ModDown combine");
+  return CKKS_OK;
+}
+
+struct KsBufs {
+  uint32_t *y, *M, *acc, *x, *z;
+};
+KsBufs ks_bufs(const Ctx& c, int L, WS& w) {
+  KsBufs b;
+  b.y = w.take(words(c, L));
+  b.M = w.take(words(c, (size_t)c.beta(L) * (L + c.k)));
+  b.acc = w.take(words(c, 2 * (size_t)(L + c.k)));
+  b.x = w.take(words(c, c.k));
+  b.z = w.take(words(c, L));
+  return b;
+}
+
+int keyswitch_impl(const Ctx& c, const uint32_t* d, int L, const uint32_t* evk, uint32_t* out,
+                   const uint32_t* add0, const uint32_t* add1, WS& w, hipStream_t st) {
+  const size_t N = c.N;
+  const int R = L + c.k;
+  KsBufs b = ks_bufs(c, L, w);
+  int rc = modup_impl(c, d, L, b.M, b.y, st);
+  if (rc) return rc;
+  CKKS_TRY(launch_inner_product(c, c.rows(L), b.M, c.beta(L), R, evk, b.acc, st), "inner product");
+  if ((rc = moddown_impl(c, b.acc, L, add0, out, b.x, b.z, st))) return rc;
+  return moddown_impl(c, b.acc + (size_t)R * N, L, add1, out + (size_t)L * N, b.x, b.z, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ckks_last_error(void) { return g_err.c_str(); }
+
+int ckks_ctx_create(ckks_ctx** out, int logN, const uint32_t* h_q, int L_max, const uint32_t* h_p,
+                    int k, int dnum, int device) {
+  if (!out || !h_q || !h_p) return fail(CKKS_EINVAL, "null argument");
+  *out = nullptr;
+  if (logN < kMinLogN || logN > kMaxLogN)
+    return fail(CKKS_EUNSUPPORTED, "logN must be in [12, 16]");
+  if (L_max < 1 || k < 1 || dnum < 1 || L_max + k > kMaxPrimes)
+    return fail(CKKS_EINVAL, "need L_max >= 1, k >= 1, dnum >= 1, L_max + k <= 64");
+  const int alpha = (L_max + dnum - 1) / dnum;
+  if (alpha != k) return fail(CKKS_EINVAL, "digit size ceil(L_max / dnum) must equal k");
+  if (alpha > kMaxAlpha) return fail(CKKS_EUNSUPPORTED, "digit size above 16");
+  if ((L_max + alpha - 1) / alpha > 15)
+    return fail(CKKS_EUNSUPPORTED, "more than 15 digits (64-bit inner-product accumulator)");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(CKKS_EINVAL, "no such HIP device");
+  DeviceGuard g(device);
+  if (!g.ok) return fail(CKKS_EHIP, "hipSetDevice failed");
+  ckks_ctx* ctx = new (std::nothrow) ckks_ctx;
+  if (!ctx) return fail(CKKS_ENOMEM, "host allocation failed");
+  Ctx& c = ctx->c;
+  c.device = device;
+  c.logN = logN;
+  c.N = 1 << logN;
+  c.L_max = L_max;
+  c.k = k;
+  c.dnum = dnum;
+  c.alpha = alpha;
+  int code = CKKS_OK;
+  const std::string err = build_tables(c, h_q, h_p, &code);
+  if (code != CKKS_OK) {
+    free_tables(c);
+    delete ctx;
+    return fail(code, err);
+  }
+  *out = ctx;
+  return CKKS_OK;
+}
+
+int ckks_ctx_destroy(ckks_ctx* ctx) {
+  if (!ctx) return CKKS_OK;
+  DeviceGuard g(ctx->c.device);
+  free_tables(ctx->c);
+  delete ctx;
+  return CKKS_OK;
+}
+
+size_t ckks_workspace_bytes(const ckks_ctx* ctx, int op, int L) {
+  if (!ctx || L < 1 || L > ctx->c.L_max) return 0;
+  return ws_bytes(ctx->c, op, L);
+}
+
+static int ntt_common(const ckks_ctx* ctx, uint32_t* a, int L, int with_P, void* stream, bool inv) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!a) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  DeviceGuard g(c.device);
+  const int rows = L + (with_P ? c.k : 0);
+  const hipStream_t st = (hipStream_t)stream;
+  if (inv)
+    CKKS_TRY(launch_intt(c, a, a, rows, c.rows(L), 0, 0, nullptr, 0, st), "INTT");
+  else
+    CKKS_TRY(launch_ntt(c, a, a, rows, c.rows(L), 0, 0, st), "NTT");
+  return CKKS_OK;
+}
+
+int ckks_ntt(const ckks_ctx* ctx, uint32_t* a, int L, int with_P, void* stream) {
+  return ntt_common(ctx, a, L, with_P, stream, false);
+}
+
+int ckks_intt(const ckks_ctx* ctx, uint32_t* a, int L, int with_P, void* stream) {
+  return ntt_common(ctx, a, L, with_P, stream, true);
+}
+
+int ckks_automorph(const ckks_ctx* ctx, const uint32_t* in, uint32_t* out, int rows, int rot,
+                   void* stream) {
+  if (!ctx) return fail(CKKS_EINVAL, "null context");
+  if (!in || !out || rows < 1) return fail(CKKS_EINVAL, "bad automorphism arguments");
+  if (in == out) return fail(CKKS_EINVAL, "automorphism output aliases its input");
+  const Ctx& c = ctx->c;
+  DeviceGuard g(c.device);
+  CKKS_TRY(launch_automorph(c, in, out, rows, galois(c, rot), (hipStream_t)stream), "automorphism");
+  return CKKS_OK;
+}
+
+int ckks_tensor(const ckks_ctx* ctx, const uint32_t* ct1, const uint32_t* ct2, int L, uint32_t* out,
+                void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!ct1 || !ct2 || !out) return fail(CKKS_EINVAL, "null data pointer");
+  DeviceGuard g(ctx->c.device);
+  CKKS_TRY(launch_tensor(ctx->c, ct1, ct2, L, out, (hipStream_t)stream), "tensor");
+  return CKKS_OK;
+}
+
+int ckks_modup(const ckks_ctx* ctx, const uint32_t* d, int L, uint32_t* out, void* ws,
+               size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!d || !out) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  if ((rc = check_ws(c, CKKS_OP_MODUP, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  WS w{(char*)ws, ws_bytes_given};
+  return modup_impl(c, d, L, out, w.take(words(c, L)), (hipStream_t)stream);
+}
+
+int ckks_inner_product(const ckks_ctx* ctx, const uint32_t* M, int L, const uint32_t* evk,
+                       uint32_t* acc, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!M || !evk || !acc) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  DeviceGuard g(c.device);
+  CKKS_TRY(launch_inner_product(c, c.rows(L), M, c.beta(L), L + c.k, evk, acc, (hipStream_t)stream),
+           "inner product");
+  return CKKS_OK;
+}
+
+int ckks_moddown(const ckks_ctx* ctx, const uint32_t* in, int L, uint32_t* out, void* ws,
+                 size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!in || !out) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  if ((rc = check_ws(c, CKKS_OP_MODDOWN, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  WS w{(char*)ws, ws_bytes_given};
+  uint32_t* x = w.take(words(c, c.k));
+  uint32_t* z = w.take(words(c, L));
+  return moddown_impl(c, in, L, nullptr, out, x, z, (hipStream_t)stream);
+}
+
+int ckks_keyswitch(const ckks_ctx* ctx, const uint32_t* d, int L, const uint32_t* evk,
+                   uint32_t* out, void* ws, size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!d || !evk || !out) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  if ((rc = check_ws(c, CKKS_OP_KEYSWITCH, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  WS w{(char*)ws, ws_bytes_given};
+  return keyswitch_impl(c, d, L, evk, out, nullptr, nullptr, w, (hipStream_t)stream);
+}
+
+int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct1, const uint32_t* ct2, int L,
+               const uint32_t* rlk, uint32_t* out, void* ws, size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!ct1 || !ct2 || !rlk || !out) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  if ((rc = check_ws(c, CKKS_OP_HMULT, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t N = c.N;
+  WS w{(char*)ws, ws_bytes_given};
+  uint32_t* d = w.take(words(c, 3 * (size_t)L));
+  CKKS_TRY(launch_tensor(c, ct1, ct2, L, d, st), "tensor");
+  return keyswitch_impl(c, d + 2 * L * N, L, rlk, out, d, d + L * N, w, st);
+}
+
+int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int L, int rot, const uint32_t* rotk,
+              uint32_t* out, void* ws, size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!ct || !rotk || !out) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  if ((rc = check_ws(c, CKKS_OP_HROT, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t N = c.N;
+  WS w{(char*)ws, ws_bytes_given};
+  uint32_t* sg = w.take(words(c, 2 * (size_t)L));
+  CKKS_TRY(launch_automorph(c, ct, sg, 2 * L, galois(c, rot), st), "automorphism");
+  return keyswitch_impl(c, sg + L * N, L, rotk, out, sg, nullptr, w, st);
+}
+
+int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int* h_rots, int n,
+                      const uint32_t* const* h_rotks, uint32_t* const* h_outs, void* ws,
+                      size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!ct || !h_rots || !h_rotks || !h_outs || n < 1)
+    return fail(CKKS_EINVAL, "bad hoisted-rotation arguments");
+  for (int i = 0; i < n; ++i)
+    if (!h_rotks[i] || !h_outs[i]) return fail(CKKS_EINVAL, "null key or output pointer");
+  const Ctx& c = ctx->c;
+  if ((rc = check_ws(c, CKKS_OP_HROT_HOISTED, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t N = c.N;
+  const int R = L + c.k, beta = c.beta(L);
+  WS w{(char*)ws, ws_bytes_given};
+  uint32_t* M = w.take(words(c, (size_t)beta * R));
+  uint32_t* Mg = w.take(words(c, (size_t)beta * R));
+  uint32_t* s0 = w.take(words(c, L));
+  uint32_t* acc = w.take(words(c, 2 * (size_t)R));
+  uint32_t* y = w.take(words(c, L));
+  uint32_t* x = w.take(words(c, c.k));
+  uint32_t* z = w.take(words(c, L));
+  if ((rc = modup_impl(c, ct + (size_t)L * N, L, M, y, st))) return rc;
+  for (int i = 0; i < n; ++i) {
+    const uint32_t gal = galois(c, h_rots[i]);
+    CKKS_TRY(launch_automorph(c, M, Mg, beta * R, gal, st), "automorphism");
+    CKKS_TRY(launch_automorph(c, ct, s0, L, gal, st), "automorphism");
+    CKKS_TRY(launch_inner_product(c, c.rows(L), Mg, beta, R, h_rotks[i], acc, st), "inner product");
+    if ((rc = moddown_impl(c, acc, L, s0, h_outs[i], x, z, st))) return rc;
+    if ((rc = moddown_impl(c, acc + (size_t)R * N, L, nullptr, h_outs[i] + (size_t)L * N, x, z, st)))
+      return rc;
+  }
+  return CKKS_OK;
+}
+
+int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int L, uint32_t* out, void* ws,
+                 size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L, 2);
+  if (rc) return rc;
+  if (!ct || !out) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  if ((rc = check_ws(c, CKKS_OP_RESCALE, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t N = c.N;
+  WS w{(char*)ws, ws_bytes_given};
+  uint32_t* t = w.take(words(c, 1));
+  uint32_t* bc = w.take(words(c, L));
+  for (int comp = 0; comp < 2; ++comp) {
+    const uint32_t* a = ct + (size_t)comp * L * N;
+    // the top limb alone: a one-row launch whose row maps to prime index L - 1
+    CKKS_TRY(launch_intt(c, a + (size_t)(L - 1) * N, t, 1, RowMap{0, L - 1}, 0, 0, nullptr, 0, st),
+             "rescale INTT");
+    CKKS_TRY(launch_broadcast_mod(c, L - 1, t, bc, st), "rescale broadcast");
+    CKKS_TRY(launch_ntt(c, bc, bc, L - 1, c.rows(L - 1), 0, 0, st), "rescale NTT");
+    CKKS_TRY(launch_sub_scale(c, L - 1, a, bc, c.d_rescale_inv + (size_t)L * c.L_max,
+                              out + (size_t)comp * (L - 1) * N, st),
+             "rescale combine");
+  }
+  return CKKS_OK;
+}
+
+}  // extern "C"

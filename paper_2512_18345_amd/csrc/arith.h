@@ -1,0 +1,60 @@
+// Exact 32-bit-word modular arithmetic for gfx950 (moduli q < 2^30).
+//
+// On gfx950 v_mul_lo_u32 / v_mul_hi_u32 / v_mad_u64_u32 issue at close to
+// full VALU rate, so the products below are plain 32-bit integer multiplies.
+// Lazy ranges: values may live in [0, 2q) or [0, 4q) between steps; 4q < 2^32.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ckks {
+
+// x in [0, 2m) -> [0, m): if x >= m then x - m wraps below x, else it wraps above.
+__device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t m) { return min(x, x - m); }
+
+// Shoup product y * w mod q, result in [0, 2q), for any y < 2^32, w < q and
+// wp = floor(w * 2^32 / q).
+__device__ __forceinline__ uint32_t mul_shoup(uint32_t y, uint32_t w, uint32_t wp, uint32_t q) {
+  const uint32_t qt = __umulhi(y, wp);
+  return y * w - qt * q;
+}
+
+// Cooley-Tukey butterfly (x, y) <- (x + w y, x - w y), Harvey's lazy form:
+// inputs and outputs in [0, 4q).
+__device__ __forceinline__ void bfly_ct(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp,
+                                        uint32_t q, uint32_t q2) {
+  const uint32_t xx = csub(x, q2);
+  const uint32_t t = mul_shoup(y, w, wp, q);
+  x = xx + t;
+  y = xx + q2 - t;
+}
+
+// Gentleman-Sande butterfly (x, y) <- (x + y, w (x - y)): inputs and outputs in [0, 2q).
+__device__ __forceinline__ void bfly_gs(uint32_t& x, uint32_t& y, uint32_t w, uint32_t wp,
+                                        uint32_t q, uint32_t q2) {
+  const uint32_t s = csub(x + y, q2);
+  const uint32_t d = x + q2 - y;
+  x = s;
+  y = mul_shoup(d, w, wp, q);
+}
+
+// Exact x mod q for any 64-bit x, q < 2^30, mu = floor(2^64 / q) split as
+// (mu_hi, mu_lo).  The Barrett quotient floor(x mu / 2^64) is either Q or
+// Q - 1 (Q = floor(x / q)), so x - qh q lies in [0, 2q) and is computed in
+// 32 bits; only the low word of qh is needed, which is why the 64-bit
+// partial sum may wrap.
+__device__ __forceinline__ uint32_t reduce64(uint64_t x, uint32_t q, uint32_t mu_hi,
+                                             uint32_t mu_lo) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  uint64_t s = (uint64_t)x1 * mu_lo + __umulhi(x0, mu_lo);
+  s += (uint64_t)x0 * mu_hi;
+  const uint32_t qh = x1 * mu_hi + (uint32_t)(s >> 32);
+  return csub(x0 - qh * q, q);
+}
+
+// x mod q for x < 2^32 with mu32 = floor(2^32 / q): remainder in [0, 2q), one correction.
+__device__ __forceinline__ uint32_t reduce32(uint32_t x, uint32_t q, uint32_t mu32) {
+  return csub(x - __umulhi(x, mu32) * q, q);
+}
+
+}  // namespace ckks

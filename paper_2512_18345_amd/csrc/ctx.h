@@ -1,0 +1,86 @@
+// Context (per ring degree N): device-resident tables and the launchers'
+// view of them.  Internal to the library; the public surface is ckks.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ckks.h"
+
+namespace ckks {
+
+constexpr int kTileLog = 12;            // elements per NTT work-group tile
+constexpr int kTile = 1 << kTileLog;
+constexpr int kBlockLog = 8;            // pass-2 line length (N = N1 * 256)
+constexpr int kWG = 256;                // threads per work-group
+constexpr int kMinLogN = 12, kMaxLogN = 16;
+constexpr int kMaxPrimes = 64;
+constexpr int kMaxAlpha = 16;           // digit size / special-prime count
+
+// Per-prime constants (device).
+struct ModC {
+  uint32_t q;
+  uint32_t mu32;        // floor(2^32 / q)
+  uint32_t mu_hi, mu_lo;  // floor(2^64 / q)
+  uint32_t ninv, ninv_s;  // N^-1 mod q and its Shoup companion
+};
+
+// What a kernel needs to find a prime's tables.
+struct DevTab {
+  const ModC* mod;   // [nprimes]
+  const uint2* tw;   // [nprimes][N]: (psi^brv(i), Shoup) at index i in [1, N)
+  const uint2* itw;  // [nprimes][N]: (psi^-brv(i), Shoup)
+  int logN;
+  int L_max;
+};
+
+// Rows of a launch: row r of the data is prime index pidx(r).
+struct RowMap {
+  int L;       // rows [0, L) are q_0..q_{L-1}
+  int L_max;   // rows >= L are p_{r - L}, prime index L_max + (r - L)
+  __host__ __device__ int pidx(int r) const { return r < L ? r : L_max + (r - L); }
+};
+
+struct Ctx {
+  int device;
+  int logN, N;
+  int L_max, k, dnum, alpha;
+  std::vector<uint32_t> primes;  // q_0..q_{L_max-1}, p_0..p_{k-1}
+  // host copies used to build launches
+  std::vector<ModC> h_mod;
+
+  // device tables
+  ModC* d_mod = nullptr;
+  uint2* d_tw = nullptr;
+  uint2* d_itw = nullptr;
+  // ModUp at level L (1-based): per Q row i < L, (N^-1 * (D_j/q_i)^-1, Shoup) where j = i / alpha.
+  uint2* d_modup_scale = nullptr;     // [L_max + 1][L_max]
+  // ModUp BConv tables at level L, digit j: T[r][i] = (D_j / q_{j alpha + i}) mod prime(r),
+  // r over the L + k ModUp rows.  Offsets into one buffer.
+  uint32_t* d_modup_T = nullptr;
+  std::vector<size_t> modup_T_off;    // index (L * beta_max + j)
+  // ModDown: P rows scale (N^-1 * (P/p_m)^-1, Shoup) indexed m; T_down[i][m] = (P/p_m) mod q_i;
+  // P^-1 mod q_i with Shoup.
+  uint2* d_moddown_scale = nullptr;   // [k]
+  uint32_t* d_moddown_T = nullptr;    // [L_max][k]
+  uint2* d_pinv = nullptr;            // [L_max]
+  // Rescale at level L: q_{L-1}^-1 mod q_i (Shoup), i < L - 1.
+  uint2* d_rescale_inv = nullptr;     // [L_max + 1][L_max]
+
+  DevTab tab() const { return DevTab{d_mod, d_tw, d_itw, logN, L_max}; }
+  RowMap rows(int L) const { return RowMap{L, L_max}; }
+  int beta(int L) const { return (L + alpha - 1) / alpha; }
+  int beta_max() const { return beta(L_max); }
+};
+
+// Host-side table construction (params.cpp).  Returns "" or an error message.
+std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code);
+void free_tables(Ctx& c);
+
+}  // namespace ckks
+
+struct ckks_ctx {
+  ckks::Ctx c;
+};

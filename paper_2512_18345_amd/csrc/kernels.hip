@@ -1,0 +1,545 @@
+// gfx950 kernels for the RNS-CKKS key-switching path.
+//
+// NTT (Sec. II-B1).  A limb of N = N1 * 256 words does not fit one
+// work-group's LDS, so, as in the paper's two-kernel NTT (Sec. III-D), each
+// transform is two passes over limb-major HBM rows:
+//   * column pass: the first log2(N1) Cooley-Tukey stages act on the columns
+//     j + 256 r (r < N1) of the N1 x 256 view; a work-group owns a tile of
+//     C = 4096 / N1 adjacent columns (coalesced row segments of C words);
+//   * block pass: the last 8 stages act inside contiguous 256-word blocks; a
+//     work-group owns 16 blocks (one contiguous 16 KiB tile).
+// The inverse runs the Gentleman-Sande stages in the opposite order (block
+// pass first).  Inside a tile the stages run as radix-16 register phases
+// (16 elements per thread, four stages per LDS round trip) with Harvey's lazy
+// Shoup butterflies; the LDS layouts are padded so that a wave64's accesses
+// spread over the banks.  Twiddle for butterfly group (m, i) is
+// psi^brv(m + i) (inverse: psi^-brv(m + i)).
+#include <hip/hip_runtime.h>
+
+#include "arith.h"
+#include "ctx.h"
+#include "kernels.h"
+
+namespace ckks {
+
+constexpr int kLds = 4352;  // padded tile: 4096 + 256 words (both layouts)
+
+__device__ __forceinline__ int lidx_col(int pos, int c, int C) { return pos * C + c + ((pos >> 4) << 4); }
+__device__ __forceinline__ int lidx_blk(int line, int pos) { return line * 272 + pos + (pos >> 4); }
+
+// ----- column-pass phases (stages on pos bits [blo, blo + LOGR)) -----------
+template <int LOGR, bool INV>
+__device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo,
+                                          const uint2* __restrict__ tw, uint32_t q, uint32_t q2) {
+  constexpr int R = 1 << LOGR;
+  constexpr int GPT = 16 / R;
+#pragma unroll
+  for (int gg = 0; gg < GPT; ++gg) {
+    const int g = threadIdx.x + gg * kWG;
+    const int c = g & (C - 1);
+    const int rest = g / C;
+    const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
+    uint32_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = s[lidx_col(base | (j << blo), c, C)];
+    if (!INV) {
+#pragma unroll
+      for (int kb = LOGR - 1; kb >= 0; --kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(1 << (logN1 - 1 - beta)) | (pos >> (beta + 1))];
+          bfly_ct(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < LOGR; ++kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(1 << (logN1 - 1 - beta)) | (pos >> (beta + 1))];
+          bfly_gs(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) s[lidx_col(base | (j << blo), c, C)] = v[j];
+  }
+}
+
+// ----- block-pass phases (16 lines of 256; stages on pos bits [blo, blo + LOGR)) ---
+template <int LOGR, bool INV>
+__device__ __forceinline__ void blk_phase(uint32_t* s, int N1, int blk0, int blo,
+                                          const uint2* __restrict__ tw, uint32_t q, uint32_t q2) {
+  constexpr int R = 1 << LOGR;
+  constexpr int GPT = 16 / R;
+  constexpr int NB = 8 - LOGR;
+#pragma unroll
+  for (int gg = 0; gg < GPT; ++gg) {
+    const int g = threadIdx.x + gg * kWG;
+    const int rest = g & ((1 << NB) - 1);
+    const int line = g >> NB;
+    const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
+    const int lb = N1 + blk0 + line;
+    uint32_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = s[lidx_blk(line, base | (j << blo))];
+    if (!INV) {
+#pragma unroll
+      for (int kb = LOGR - 1; kb >= 0; --kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(lb << (7 - beta)) | (pos >> (beta + 1))];
+          bfly_ct(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < LOGR; ++kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(lb << (7 - beta)) | (pos >> (beta + 1))];
+          bfly_gs(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) s[lidx_blk(line, base | (j << blo))] = v[j];
+  }
+}
+
+// All column stages of one tile, forward (high bits first) or inverse (low bits first).
+template <int LOGN1, bool INV>
+__device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
+  constexpr int C = kTile >> LOGN1;
+  constexpr int REM = LOGN1 - 4;  // 0..4
+  if (!INV) {
+    col_phase<4, false>(s, LOGN1, C, REM, tw, q, q2);
+    if constexpr (REM > 0) {
+      __syncthreads();
+      col_phase<(REM > 0 ? REM : 1), false>(s, LOGN1, C, 0, tw, q, q2);
+    }
+  } else {
+    col_phase<4, true>(s, LOGN1, C, 0, tw, q, q2);
+    if constexpr (REM > 0) {
+      __syncthreads();
+      col_phase<(REM > 0 ? REM : 1), true>(s, LOGN1, C, 4, tw, q, q2);
+    }
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ void blk_stages(uint32_t* s, int N1, int blk0, const uint2* tw,
+                                           uint32_t q, uint32_t q2) {
+  if (!INV) {
+    blk_phase<4, false>(s, N1, blk0, 4, tw, q, q2);
+    __syncthreads();
+    blk_phase<4, false>(s, N1, blk0, 0, tw, q, q2);
+  } else {
+    blk_phase<4, true>(s, N1, blk0, 0, tw, q, q2);
+    __syncthreads();
+    blk_phase<4, true>(s, N1, blk0, 4, tw, q, q2);
+  }
+}
+
+// ----- tile load / store helpers --------------------------------------------
+template <int LOGN1>
+__device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restrict__ row, int col0) {
+  constexpr int C = kTile >> LOGN1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lin = (threadIdx.x + k * kWG) * 4;
+    const int pos = lin / C, c = lin & (C - 1);
+    const uint4 v = *reinterpret_cast<const uint4*>(row + pos * 256 + col0 + c);
+    *reinterpret_cast<uint4*>(s + lidx_col(pos, c, C)) = v;
+  }
+}
+
+template <int LOGN1>
+__device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restrict__ row, int col0) {
+  constexpr int C = kTile >> LOGN1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lin = (threadIdx.x + k * kWG) * 4;
+    const int pos = lin / C, c = lin & (C - 1);
+    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) =
+        *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
+  }
+}
+
+// Block tiles: element e of the tile (e < 4096) is line e >> 8, pos e & 255.
+// Thread t owns tile elements 4t + 1024k .. +3 (k < 4) in the load/store/epilogue loops.
+__device__ __forceinline__ int blk_elem(int k) { return (threadIdx.x + k * kWG) * 4; }
+// (The block layout's 1-in-16 padding breaks 16-byte alignment, so these
+// LDS accesses stay 32-bit.)
+__device__ __forceinline__ uint4 lds_blk4(const uint32_t* s, int e) {
+  const uint32_t* p = s + lidx_blk(e >> 8, e & 255);  // 4 | e: no pad inside the quad
+  return make_uint4(p[0], p[1], p[2], p[3]);
+}
+__device__ __forceinline__ void lds_blk4_store(uint32_t* s, int e, uint4 v) {
+  uint32_t* p = s + lidx_blk(e >> 8, e & 255);
+  p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
+}
+
+__device__ __forceinline__ uint4 canon4(uint4 v, uint32_t q, uint32_t q2) {
+  v.x = csub(csub(v.x, q2), q);
+  v.y = csub(csub(v.y, q2), q);
+  v.z = csub(csub(v.z, q2), q);
+  v.w = csub(csub(v.w, q2), q);
+  return v;
+}
+
+// ============================================================================
+// NTT kernels
+// ============================================================================
+
+// Forward column pass: rows r in [0, gridDim.y) except [skip_lo, skip_hi).
+// Output lazy in [0, 4q).
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k_ntt_cols(DevTab T, RowMap rm, const uint32_t* src,
+                                                  uint32_t* dst, int skip_lo, int skip_hi) {
+  __shared__ __align__(16) uint32_t s[kLds];
+  const int r = blockIdx.y;
+  if (r >= skip_lo && r < skip_hi) return;
+  const int pi = rm.pidx(r);
+  const size_t N = (size_t)1 << T.logN;
+  const uint32_t q = T.mod[pi].q, q2 = 2 * q;
+  const int col0 = blockIdx.x * (kTile >> LOGN1);
+  load_cols<LOGN1>(s, src + r * N, col0);
+  __syncthreads();
+  col_stages<LOGN1, false>(s, T.tw + pi * N, q, q2);
+  __syncthreads();
+  store_cols<LOGN1>(s, dst + r * N, col0);
+}
+
+// Forward block pass; canonical output.
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uint32_t* src,
+                                                  uint32_t* dst, int skip_lo, int skip_hi) {
+  __shared__ __align__(16) uint32_t s[kLds];
+  const int r = blockIdx.y;
+  if (r >= skip_lo && r < skip_hi) return;
+  const int pi = rm.pidx(r);
+  const size_t N = (size_t)1 << T.logN;
+  const uint32_t q = T.mod[pi].q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t* in = src + r * N + blk0 * 256;
+  uint32_t* out = dst + r * N + blk0 * 256;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = blk_elem(k);
+    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
+  }
+  __syncthreads();
+  blk_stages<false>(s, 1 << LOGN1, blk0, T.tw + pi * N, q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = blk_elem(k);
+    *reinterpret_cast<uint4*>(out + e) = canon4(lds_blk4(s, e), q, q2);
+  }
+}
+
+// Inverse block pass (first Gentleman-Sande stages); output in [0, 2q).
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const uint32_t* src,
+                                                   uint32_t* dst, int skip_lo, int skip_hi) {
+  __shared__ __align__(16) uint32_t s[kLds];
+  const int r = blockIdx.y;
+  if (r >= skip_lo && r < skip_hi) return;
+  const int pi = rm.pidx(r);
+  const size_t N = (size_t)1 << T.logN;
+  const uint32_t q = T.mod[pi].q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t* in = src + r * N + blk0 * 256;
+  uint32_t* out = dst + r * N + blk0 * 256;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = blk_elem(k);
+    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
+  }
+  __syncthreads();
+  blk_stages<true>(s, 1 << LOGN1, blk0, T.itw + pi * N, q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = blk_elem(k);
+    *reinterpret_cast<uint4*>(out + e) = lds_blk4(s, e);
+  }
+}
+
+// Inverse column pass + per-row scale (N^-1 times an optional base-conversion
+// pre-multiplier) -> canonical output.  scale[pidx - scale_off] = (c, Shoup(c));
+// scale == nullptr means N^-1 alone.
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const uint32_t* src,
+                                                   uint32_t* dst, int skip_lo, int skip_hi,
+                                                   const uint2* scale, int scale_off) {
+  __shared__ __align__(16) uint32_t s[kLds];
+  constexpr int C = kTile >> LOGN1;
+  const int r = blockIdx.y;
+  if (r >= skip_lo && r < skip_hi) return;
+  const int pi = rm.pidx(r);
+  const size_t N = (size_t)1 << T.logN;
+  const ModC mc = T.mod[pi];
+  const uint32_t q = mc.q, q2 = 2 * q;
+  const uint2 sc = scale ? scale[pi - scale_off] : make_uint2(mc.ninv, mc.ninv_s);
+  const int col0 = blockIdx.x * C;
+  load_cols<LOGN1>(s, src + r * N, col0);
+  __syncthreads();
+  col_stages<LOGN1, true>(s, T.itw + pi * N, q, q2);
+  __syncthreads();
+  uint32_t* row = dst + r * N;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lin = (threadIdx.x + k * kWG) * 4;
+    const int pos = lin / C, c = lin & (C - 1);
+    uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
+    v.x = csub(mul_shoup(v.x, sc.x, sc.y, q), q);
+    v.y = csub(mul_shoup(v.y, sc.x, sc.y, q), q);
+    v.z = csub(mul_shoup(v.z, sc.x, sc.y, q), q);
+    v.w = csub(mul_shoup(v.w, sc.x, sc.y, q), q);
+    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) = v;
+  }
+}
+
+// ============================================================================
+// Base conversion (Sec. II-B2, III-C2): z_r = sum_i y_i * T[r][i] mod prime(r),
+// y canonical coefficient-domain rows (pre-multiplied already), one 64-bit
+// accumulation and a single reduction per output (overflow-free by the
+// bound checked at context creation).
+// ============================================================================
+template <int NIN>
+__global__ __launch_bounds__(kWG) void k_bconv(DevTab T, RowMap rm, const uint32_t* y, int nin,
+                                               uint32_t* out, int nrows, int skip_lo, int skip_hi,
+                                               const uint32_t* Tt, int tstride, int rows_per_block) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  uint32_t x[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) x[i] = i < nin ? y[i * N + n] : 0u;
+  const int r0 = blockIdx.y * rows_per_block;
+  const int r1 = min(r0 + rows_per_block, nrows);
+  for (int r = r0; r < r1; ++r) {
+    if (r >= skip_lo && r < skip_hi) continue;
+    const ModC mc = T.mod[rm.pidx(r)];
+    const uint32_t* t = Tt + (size_t)r * tstride;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i)
+      if (i < nin) acc += (uint64_t)x[i] * t[i];
+    out[r * N + n] = reduce64(acc, mc.q, mc.mu_hi, mc.mu_lo);
+  }
+}
+
+// ============================================================================
+// Element-wise kernels (Sec. II-B3)
+// ============================================================================
+
+// acc[c][r] = sum_j M[j][r] * evk[j][c][krow(r)] (Sec. IV-B stage 2).
+__global__ __launch_bounds__(kWG) void k_inner_product(DevTab T, RowMap rm, const uint32_t* M,
+                                                       int beta, int nrows, const uint32_t* evk,
+                                                       uint32_t* acc) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const int r = blockIdx.y;
+  const int pi = rm.pidx(r);
+  const ModC mc = T.mod[pi];
+  const size_t krows = (size_t)(T.L_max + (nrows - rm.L));
+  uint64_t a0 = 0, a1 = 0;
+  for (int j = 0; j < beta; ++j) {
+    const uint32_t m = M[((size_t)j * nrows + r) * N + n];
+    const uint32_t* e = evk + (size_t)j * 2 * krows * N + (size_t)pi * N + n;
+    a0 += (uint64_t)m * e[0];
+    a1 += (uint64_t)m * e[krows * N];
+  }
+  acc[(size_t)r * N + n] = reduce64(a0, mc.q, mc.mu_hi, mc.mu_lo);
+  acc[((size_t)nrows + r) * N + n] = reduce64(a1, mc.q, mc.mu_hi, mc.mu_lo);
+}
+
+// d0 = c0 c0', d1 = c0 c1' + c1 c0', d2 = c1 c1' over [L][N].
+__global__ __launch_bounds__(kWG) void k_tensor(DevTab T, const uint32_t* ct1, const uint32_t* ct2,
+                                                int L, uint32_t* out) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const int r = blockIdx.y;
+  const ModC mc = T.mod[r];
+  const size_t e = (size_t)r * N + n, P = (size_t)L * N;
+  const uint32_t a0 = ct1[e], a1 = ct1[P + e], b0 = ct2[e], b1 = ct2[P + e];
+  out[e] = reduce64((uint64_t)a0 * b0, mc.q, mc.mu_hi, mc.mu_lo);
+  out[P + e] = reduce64((uint64_t)a0 * b1 + (uint64_t)a1 * b0, mc.q, mc.mu_hi, mc.mu_lo);
+  out[2 * P + e] = reduce64((uint64_t)a1 * b1, mc.q, mc.mu_hi, mc.mu_lo);
+}
+
+// Eval-domain automorphism: out[r][j] = in[r][j'], 2 brv(j') + 1 = g (2 brv(j) + 1) mod 2N.
+__global__ __launch_bounds__(kWG) void k_automorph(int logN, const uint32_t* in, uint32_t* out,
+                                                   int rows, uint32_t g, int rows_per_block) {
+  const size_t N = (size_t)1 << logN;
+  const uint32_t j = blockIdx.x * kWG + threadIdx.x;
+  const uint32_t mask2n = (uint32_t)(2 * N - 1);
+  const uint32_t bj = __builtin_bitreverse32(j) >> (32 - logN);
+  const uint32_t e = (g * (2 * bj + 1)) & mask2n;
+  const uint32_t src = __builtin_bitreverse32((e - 1) >> 1) >> (32 - logN);
+  const int r0 = blockIdx.y * rows_per_block;
+  const int r1 = min(r0 + rows_per_block, rows);
+  for (int r = r0; r < r1; ++r) out[(size_t)r * N + j] = in[(size_t)r * N + src];
+}
+
+// out_i = (acc_i - z_i) * P^-1 (+ add_i) mod q_i: the ModDown combine (floor form).
+__global__ __launch_bounds__(kWG) void k_moddown_combine(DevTab T, const uint32_t* acc,
+                                                         const uint32_t* z, const uint2* pinv,
+                                                         const uint32_t* add, uint32_t* out) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const int i = blockIdx.y;
+  const uint32_t q = T.mod[i].q;
+  const size_t e = (size_t)i * N + n;
+  const uint2 pv = pinv[i];
+  uint32_t v = csub(mul_shoup(acc[e] + q - z[e], pv.x, pv.y, q), q);
+  if (add) v = csub(v + add[e], q);
+  out[e] = v;
+}
+
+// out = a + b mod q_r over [rows][N] (rows are Q rows 0..rows-1).
+__global__ __launch_bounds__(kWG) void k_add(DevTab T, const uint32_t* a, const uint32_t* b,
+                                             uint32_t* out) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t e = (size_t)blockIdx.y * N + (size_t)blockIdx.x * kWG + threadIdx.x;
+  out[e] = csub(a[e] + b[e], T.mod[blockIdx.y].q);
+}
+
+// Rescale helpers: bc[i][n] = t[n] mod q_i (i < rows), t canonical mod q_top.
+__global__ __launch_bounds__(kWG) void k_broadcast_mod(DevTab T, const uint32_t* t, uint32_t* bc) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const ModC mc = T.mod[blockIdx.y];
+  bc[(size_t)blockIdx.y * N + n] = reduce32(t[n], mc.q, mc.mu32);
+}
+
+// out_i = (a_i - v_i) * qinv_i mod q_i.
+__global__ __launch_bounds__(kWG) void k_sub_scale(DevTab T, const uint32_t* a, const uint32_t* v,
+                                                   const uint2* qinv, uint32_t* out) {
+  const size_t N = (size_t)1 << T.logN;
+  const int i = blockIdx.y;
+  const size_t e = (size_t)i * N + (size_t)blockIdx.x * kWG + threadIdx.x;
+  const uint32_t q = T.mod[i].q;
+  const uint2 c = qinv[i];
+  out[e] = csub(mul_shoup(a[e] + q - v[e], c.x, c.y, q), q);
+}
+
+// ============================================================================
+// Launchers
+// ============================================================================
+#define CKKS_DISPATCH_LOGN1(logN1, CALL) \
+  switch (logN1) {                       \
+    case 4: CALL(4); break;              \
+    case 5: CALL(5); break;              \
+    case 6: CALL(6); break;              \
+    case 7: CALL(7); break;              \
+    case 8: CALL(8); break;              \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_ntt(const Ctx& c, const uint32_t* src, uint32_t* dst, int rows, RowMap rm,
+                      int skip_lo, int skip_hi, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int logN1 = c.logN - kBlockLog;
+  const dim3 grid(c.N / kTile, rows);
+#define CALL(L1)                                                                              \
+  k_ntt_cols<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, src, dst, skip_lo, skip_hi);             \
+  k_ntt_blks<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, dst, dst, skip_lo, skip_hi);
+  CKKS_DISPATCH_LOGN1(logN1, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_intt(const Ctx& c, const uint32_t* src, uint32_t* dst, int rows, RowMap rm,
+                       int skip_lo, int skip_hi, const uint2* scale, int scale_off,
+                       hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int logN1 = c.logN - kBlockLog;
+  const dim3 grid(c.N / kTile, rows);
+#define CALL(L1)                                                                              \
+  k_intt_blks<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, src, dst, skip_lo, skip_hi);            \
+  k_intt_cols<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, dst, dst, skip_lo, skip_hi, scale, scale_off);
+  CKKS_DISPATCH_LOGN1(logN1, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_bconv(const Ctx& c, RowMap rm, const uint32_t* y, int nin, uint32_t* out,
+                        int nrows, int skip_lo, int skip_hi, const uint32_t* Tt, int tstride,
+                        hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  const int rpb = 4;
+  const dim3 grid(c.N / kWG, (nrows + rpb - 1) / rpb);
+  if (nin <= 4)
+    k_bconv<4><<<grid, kWG, 0, st>>>(c.tab(), rm, y, nin, out, nrows, skip_lo, skip_hi, Tt, tstride, rpb);
+  else if (nin <= 8)
+    k_bconv<8><<<grid, kWG, 0, st>>>(c.tab(), rm, y, nin, out, nrows, skip_lo, skip_hi, Tt, tstride, rpb);
+  else if (nin <= 12)
+    k_bconv<12><<<grid, kWG, 0, st>>>(c.tab(), rm, y, nin, out, nrows, skip_lo, skip_hi, Tt, tstride, rpb);
+  else if (nin <= 16)
+    k_bconv<16><<<grid, kWG, 0, st>>>(c.tab(), rm, y, nin, out, nrows, skip_lo, skip_hi, Tt, tstride, rpb);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_product(const Ctx& c, RowMap rm, const uint32_t* M, int beta, int nrows,
+                                const uint32_t* evk, uint32_t* acc, hipStream_t st) {
+  k_inner_product<<<dim3(c.N / kWG, nrows), kWG, 0, st>>>(c.tab(), rm, M, beta, nrows, evk, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_tensor(const Ctx& c, const uint32_t* ct1, const uint32_t* ct2, int L,
+                         uint32_t* out, hipStream_t st) {
+  k_tensor<<<dim3(c.N / kWG, L), kWG, 0, st>>>(c.tab(), ct1, ct2, L, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_automorph(const Ctx& c, const uint32_t* in, uint32_t* out, int rows, uint32_t g,
+                            hipStream_t st) {
+  const int rpb = 4;
+  k_automorph<<<dim3(c.N / kWG, (rows + rpb - 1) / rpb), kWG, 0, st>>>(c.logN, in, out, rows, g, rpb);
+  return hipGetLastError();
+}
+
+hipError_t launch_moddown_combine(const Ctx& c, int L, const uint32_t* acc, const uint32_t* z,
+                                  const uint32_t* add, uint32_t* out, hipStream_t st) {
+  k_moddown_combine<<<dim3(c.N / kWG, L), kWG, 0, st>>>(c.tab(), acc, z, c.d_pinv, add, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(const Ctx& c, int rows, const uint32_t* a, const uint32_t* b, uint32_t* out,
+                      hipStream_t st) {
+  k_add<<<dim3(c.N / kWG, rows), kWG, 0, st>>>(c.tab(), a, b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_broadcast_mod(const Ctx& c, int rows, const uint32_t* t, uint32_t* bc,
+                                hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  k_broadcast_mod<<<dim3(c.N / kWG, rows), kWG, 0, st>>>(c.tab(), t, bc);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_scale(const Ctx& c, int rows, const uint32_t* a, const uint32_t* v,
+                            const uint2* qinv, uint32_t* out, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  k_sub_scale<<<dim3(c.N / kWG, rows), kWG, 0, st>>>(c.tab(), a, v, qinv, out);
+  return hipGetLastError();
+}
+
+}  // namespace ckks
