@@ -10,6 +10,7 @@
 #include <string>
 
 #include "ctx.h"
+#include "keyswitch.h"
 #include "kernels.h"
 
 using namespace ckks;
@@ -65,22 +66,23 @@ size_t words(const Ctx& c, size_t rows) { return rows * (size_t)c.N; }
 
 size_t ws_modup(const Ctx& c, int L) { return round_up(words(c, L) * 4); }
 size_t ws_moddown(const Ctx& c, int L) { return round_up(words(c, c.k) * 4) + round_up(words(c, L) * 4); }
-size_t ws_keyswitch(const Ctx& c, int L) {
-  return ws_modup(c, L) + round_up(words(c, (size_t)c.beta(L) * (L + c.k)) * 4) +
-         round_up(words(c, 2 * (size_t)(L + c.k)) * 4) + ws_moddown(c, L);
+size_t ws_keyswitch(const Ctx& c, int L) { return round_up(ks_ws_words(c, L) * 4); }
+size_t ws_hoisted(const Ctx& c, int L) {
+  // the shared ModUp output and its scratch, plus one KS_HOIST scratch per
+  // rotation of a chunk of up to kInlineJobs rotations
+  return round_up(words(c, (size_t)c.beta(L) * (L + c.k)) * 4) + ws_modup(c, L) +
+         (size_t)kInlineJobs * round_up(ks_hoist_ws_words(c, L) * 4);
 }
 size_t ws_bytes(const Ctx& c, int op, int L) {
   switch (op) {
     case CKKS_OP_NTT: return 0;
     case CKKS_OP_MODUP: return ws_modup(c, L);
     case CKKS_OP_MODDOWN: return ws_moddown(c, L);
-    case CKKS_OP_KEYSWITCH: return ws_keyswitch(c, L);
-    case CKKS_OP_HMULT: return round_up(words(c, 3 * (size_t)L) * 4) + ws_keyswitch(c, L);
-    case CKKS_OP_HROT: return round_up(words(c, 2 * (size_t)L) * 4) + ws_keyswitch(c, L);
-    case CKKS_OP_HROT_HOISTED:
-      return 2 * round_up(words(c, (size_t)c.beta(L) * (L + c.k)) * 4) + round_up(words(c, L) * 4) +
-             round_up(words(c, 2 * (size_t)(L + c.k)) * 4) + ws_modup(c, L) + ws_moddown(c, L);
-    case CKKS_OP_RESCALE: return round_up(words(c, 1) * 4) + round_up(words(c, L) * 4);
+    case CKKS_OP_KEYSWITCH:
+    case CKKS_OP_HMULT:
+    case CKKS_OP_HROT: return ws_keyswitch(c, L);
+    case CKKS_OP_HROT_HOISTED: return ws_hoisted(c, L);
+    case CKKS_OP_RESCALE: return round_up(rs_ws_words(c, L) * 4);
     default: return 0;
   }
 }
@@ -151,29 +153,14 @@ int moddown_impl(const Ctx& c, const uint32_t* a, int L, const uint32_t* add, ui
   return CKKS_OK;
 }
 
-struct KsBufs {
-  uint32_t *y, *M, *acc, *x, *z;
-};
-KsBufs ks_bufs(const Ctx& c, int L, WS& w) {
-  KsBufs b;
-  b.y = w.take(words(c, L));
-  b.M = w.take(words(c, (size_t)c.beta(L) * (L + c.k)));
-  b.acc = w.take(words(c, 2 * (size_t)(L + c.k)));
-  b.x = w.take(words(c, c.k));
-  b.z = w.take(words(c, L));
-  return b;
-}
-
-int keyswitch_impl(const Ctx& c, const uint32_t* d, int L, const uint32_t* evk, uint32_t* out,
-                   const uint32_t* add0, const uint32_t* add1, WS& w, hipStream_t st) {
-  const size_t N = c.N;
-  const int R = L + c.k;
-  KsBufs b = ks_bufs(c, L, w);
-  int rc = modup_impl(c, d, L, b.M, b.y, st);
-  if (rc) return rc;
-  CKKS_TRY(launch_inner_product(c, c.rows(L), b.M, c.beta(L), R, evk, b.acc, st), "inner product");
-  if ((rc = moddown_impl(c, b.acc, L, add0, out, b.x, b.z, st))) return rc;
-  return moddown_impl(c, b.acc + (size_t)R * N, L, add1, out + (size_t)L * N, b.x, b.z, st);
+// One job through the fused pipeline.
+int run_one(const Ctx& c, int kind, int L, uint32_t gal, const uint32_t* a, const uint32_t* b,
+            const uint32_t* key, uint32_t* out, void* ws, hipStream_t st) {
+  JobArg<KsJob> ja{};
+  ja.table = nullptr;
+  ja.inl[0] = KsJob{kind, L, gal, 0, a, b, key, out, (uint32_t*)ws};
+  CKKS_TRY(ks_launch(c, ja, 1, L, true, false, st), "key-switching pipeline");
+  return CKKS_OK;
 }
 
 }  // namespace
@@ -324,8 +311,7 @@ int ckks_keyswitch(const ckks_ctx* ctx, const uint32_t* d, int L, const uint32_t
   const Ctx& c = ctx->c;
   if ((rc = check_ws(c, CKKS_OP_KEYSWITCH, L, ws, ws_bytes_given))) return rc;
   DeviceGuard g(c.device);
-  WS w{(char*)ws, ws_bytes_given};
-  return keyswitch_impl(c, d, L, evk, out, nullptr, nullptr, w, (hipStream_t)stream);
+  return run_one(c, KS_PLAIN, L, 0, d, nullptr, evk, out, ws, (hipStream_t)stream);
 }
 
 int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct1, const uint32_t* ct2, int L,
@@ -336,12 +322,7 @@ int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct1, const uint32_t* ct2, in
   const Ctx& c = ctx->c;
   if ((rc = check_ws(c, CKKS_OP_HMULT, L, ws, ws_bytes_given))) return rc;
   DeviceGuard g(c.device);
-  const hipStream_t st = (hipStream_t)stream;
-  const size_t N = c.N;
-  WS w{(char*)ws, ws_bytes_given};
-  uint32_t* d = w.take(words(c, 3 * (size_t)L));
-  CKKS_TRY(launch_tensor(c, ct1, ct2, L, d, st), "tensor");
-  return keyswitch_impl(c, d + 2 * L * N, L, rlk, out, d, d + L * N, w, st);
+  return run_one(c, KS_HMULT, L, 0, ct1, ct2, rlk, out, ws, (hipStream_t)stream);
 }
 
 int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int L, int rot, const uint32_t* rotk,
@@ -352,12 +333,7 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int L, int rot, const uin
   const Ctx& c = ctx->c;
   if ((rc = check_ws(c, CKKS_OP_HROT, L, ws, ws_bytes_given))) return rc;
   DeviceGuard g(c.device);
-  const hipStream_t st = (hipStream_t)stream;
-  const size_t N = c.N;
-  WS w{(char*)ws, ws_bytes_given};
-  uint32_t* sg = w.take(words(c, 2 * (size_t)L));
-  CKKS_TRY(launch_automorph(c, ct, sg, 2 * L, galois(c, rot), st), "automorphism");
-  return keyswitch_impl(c, sg + L * N, L, rotk, out, sg, nullptr, w, st);
+  return run_one(c, KS_HROT, L, galois(c, rot), ct, nullptr, rotk, out, ws, (hipStream_t)stream);
 }
 
 int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int* h_rots, int n,
@@ -374,24 +350,20 @@ int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int*
   DeviceGuard g(c.device);
   const hipStream_t st = (hipStream_t)stream;
   const size_t N = c.N;
-  const int R = L + c.k, beta = c.beta(L);
   WS w{(char*)ws, ws_bytes_given};
-  uint32_t* M = w.take(words(c, (size_t)beta * R));
-  uint32_t* Mg = w.take(words(c, (size_t)beta * R));
-  uint32_t* s0 = w.take(words(c, L));
-  uint32_t* acc = w.take(words(c, 2 * (size_t)R));
+  uint32_t* M = w.take(words(c, (size_t)c.beta(L) * (L + c.k)));
   uint32_t* y = w.take(words(c, L));
-  uint32_t* x = w.take(words(c, c.k));
-  uint32_t* z = w.take(words(c, L));
   if ((rc = modup_impl(c, ct + (size_t)L * N, L, M, y, st))) return rc;
-  for (int i = 0; i < n; ++i) {
-    const uint32_t gal = galois(c, h_rots[i]);
-    CKKS_TRY(launch_automorph(c, M, Mg, beta * R, gal, st), "automorphism");
-    CKKS_TRY(launch_automorph(c, ct, s0, L, gal, st), "automorphism");
-    CKKS_TRY(launch_inner_product(c, c.rows(L), Mg, beta, R, h_rotks[i], acc, st), "inner product");
-    if ((rc = moddown_impl(c, acc, L, s0, h_outs[i], x, z, st))) return rc;
-    if ((rc = moddown_impl(c, acc + (size_t)R * N, L, nullptr, h_outs[i] + (size_t)L * N, x, z, st)))
-      return rc;
+  uint32_t* job_ws[kInlineJobs];
+  for (int i = 0; i < kInlineJobs; ++i) job_ws[i] = w.take(ks_hoist_ws_words(c, L));
+  for (int i0 = 0; i0 < n; i0 += kInlineJobs) {
+    const int cnt = std::min(kInlineJobs, n - i0);
+    JobArg<KsJob> ja{};
+    ja.table = nullptr;
+    for (int t = 0; t < cnt; ++t)
+      ja.inl[t] = KsJob{KS_HOIST, L, galois(c, h_rots[i0 + t]), 0, ct, M, h_rotks[i0 + t],
+                        h_outs[i0 + t], job_ws[t]};
+    CKKS_TRY(ks_launch(c, ja, cnt, L, false, true, st), "hoisted rotations");
   }
   return CKKS_OK;
 }
@@ -404,22 +376,10 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int L, uint32_t* out, 
   const Ctx& c = ctx->c;
   if ((rc = check_ws(c, CKKS_OP_RESCALE, L, ws, ws_bytes_given))) return rc;
   DeviceGuard g(c.device);
-  const hipStream_t st = (hipStream_t)stream;
-  const size_t N = c.N;
-  WS w{(char*)ws, ws_bytes_given};
-  uint32_t* t = w.take(words(c, 1));
-  uint32_t* bc = w.take(words(c, L));
-  for (int comp = 0; comp < 2; ++comp) {
-    const uint32_t* a = ct + (size_t)comp * L * N;
-    // the top limb alone: a one-row launch whose row maps to prime index L - 1
-    CKKS_TRY(launch_intt(c, a + (size_t)(L - 1) * N, t, 1, RowMap{0, L - 1}, 0, 0, nullptr, 0, st),
-             "rescale INTT");
-    CKKS_TRY(launch_broadcast_mod(c, L - 1, t, bc, st), "rescale broadcast");
-    CKKS_TRY(launch_ntt(c, bc, bc, L - 1, c.rows(L - 1), 0, 0, st), "rescale NTT");
-    CKKS_TRY(launch_sub_scale(c, L - 1, a, bc, c.d_rescale_inv + (size_t)L * c.L_max,
-                              out + (size_t)comp * (L - 1) * N, st),
-             "rescale combine");
-  }
+  JobArg<RsJob> ja{};
+  ja.table = nullptr;
+  ja.inl[0] = RsJob{L, {0, 0, 0}, ct, out, (uint32_t*)ws, nullptr};
+  CKKS_TRY(rs_launch(c, ja, 1, L, (hipStream_t)stream), "rescale");
   return CKKS_OK;
 }
 

@@ -57,4 +57,18 @@ __device__ __forceinline__ uint32_t reduce32(uint32_t x, uint32_t q, uint32_t mu
   return csub(x - __umulhi(x, mu32) * q, q);
 }
 
+// Load through the constant address space: for a work-group-uniform address
+// this becomes a scalar (s_load) read.  Only for tables that no kernel writes.
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized tables only");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  cword* s = (cword*)p;
+  T v;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) d[i] = s[i];
+  return v;
+}
+
 }  // namespace ckks

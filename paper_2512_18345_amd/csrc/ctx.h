@@ -61,6 +61,7 @@ struct Ctx {
   // r over the L + k ModUp rows.  Offsets into one buffer.
   uint32_t* d_modup_T = nullptr;
   std::vector<size_t> modup_T_off;    // index (L * beta_max + j)
+  uint32_t* d_modup_T_off = nullptr;  // device copy of modup_T_off
   // ModDown: P rows scale (N^-1 * (P/p_m)^-1, Shoup) indexed m; T_down[i][m] = (P/p_m) mod q_i;
   // P^-1 mod q_i with Shoup.
   uint2* d_moddown_scale = nullptr;   // [k]

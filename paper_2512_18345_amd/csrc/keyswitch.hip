@@ -1,0 +1,719 @@
+// Fused key-switching pipeline over a job table (see keyswitch.h).
+//
+// Key-switching has three stages (Fig. keysw): ModUp of every digit, the
+// inner product with the evaluation key, ModDown of both components.  The NTT
+// is row-parallel and BConv column-parallel, so they cannot share a kernel
+// (Sec. III-D); what does fuse here is everything element-wise around them:
+//
+//  K1  INTT block pass of the input (loader forms d: d, c1*c1', or sigma(c1))
+//  K2  INTT column pass + N^-1 (D_j/q_i)^-1 pre-multiply            -> y
+//  K3  ModUp BConv, every digit in one launch                        -> z
+//  K4  NTT column pass of every digit's new rows                     -> z
+//  K5  NTT block pass fused with the inner product over the digits
+//      (digit rows come straight from the loader; hoisted jobs gather
+//      sigma(M) instead of transforming), then, for the P rows, the first
+//      INTT pass of ModDown                                          -> acc
+//  K6  INTT column pass of the P rows, N^-1 (P/p_m)^-1 pre-multiply  -> x
+//  K7  ModDown BConv P -> Q, both components                        -> w
+//  K8  NTT column pass of w
+//  K9  NTT block pass fused with (acc - w) P^-1 plus the epilogue
+//      term (d0 / d1 of HMult, sigma(c0) of HRot)                    -> out
+//
+// Every launch covers all jobs (grid.z) and all rows of a stage, which is
+// what gives small levels enough work-groups (the batching argument of
+// Sec. IV-A).  Rescale has its own four kernels (R1..R4).
+#include <hip/hip_runtime.h>
+
+#include "arith.h"
+#include "ctx.h"
+#include "keyswitch.h"
+#include "ntt_tile.h"
+
+namespace ckks {
+
+namespace {
+
+struct KsConst {
+  DevTab T;
+  int k, alpha, beta_max;
+  const uint2* modup_scale;
+  const uint32_t* modup_T;
+  const uint32_t* modup_T_off;
+  const uint2* moddown_scale;
+  const uint32_t* moddown_T;
+  const uint2* pinv;
+  const uint2* rescale_inv;
+};
+
+KsConst make_const(const Ctx& c) {
+  return KsConst{c.tab(), c.k, c.alpha, c.beta_max(), c.d_modup_scale, c.d_modup_T,
+                 c.d_modup_T_off, c.d_moddown_scale, c.d_moddown_T, c.d_pinv, c.d_rescale_inv};
+}
+
+// Scratch layout of one job (rows of N words): acc [2][R], x [2][k], w [2][L],
+// then, for jobs that run ModUp, y [L], z [beta][R] and de [L] (the eval-domain
+// polynomial being switched, kept by K1 for the digit rows of K5); R = L + k.
+struct KsView {
+  uint32_t *y, *z, *de, *acc, *x, *w;
+  int L, R, beta;
+};
+
+__device__ __forceinline__ KsView ks_view(const KsJob& J, const KsConst& K, size_t N) {
+  KsView v;
+  v.L = J.L;
+  v.R = J.L + K.k;
+  v.beta = (J.L + K.alpha - 1) / K.alpha;
+  v.acc = J.ws;
+  v.x = v.acc + (size_t)2 * v.R * N;
+  v.w = v.x + (size_t)2 * K.k * N;
+  v.y = v.w + (size_t)2 * v.L * N;
+  v.z = v.y + (size_t)v.L * N;
+  v.de = v.z + (size_t)v.beta * v.R * N;
+  return v;
+}
+
+__device__ __forceinline__ int ks_pidx(int r, int L, int L_max) { return r < L ? r : L_max + (r - L); }
+
+// Source index of the eval-domain automorphism: out[j] = in[auto_src(j)].
+__device__ __forceinline__ uint32_t auto_src(uint32_t j, uint32_t g, int logN) {
+  const uint32_t bj = __builtin_bitreverse32(j) >> (32 - logN);
+  const uint32_t e = (g * (2u * bj + 1u)) & ((2u << logN) - 1u);
+  return __builtin_bitreverse32((e - 1u) >> 1) >> (32 - logN);
+}
+
+__device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const ModC& m) {
+  return reduce64((uint64_t)a * b, m.q, m.mu_hi, m.mu_lo);
+}
+
+// Four consecutive eval-domain words n..n+3 of row r of the polynomial a job
+// key-switches: d (PLAIN), c1 c1' (HMULT), sigma(c1) (HROT / HOIST).
+__device__ __forceinline__ uint4 load_d4(const KsJob& J, int r, uint32_t n, size_t N, int logN,
+                                         const ModC& m) {
+  if (J.kind == KS_PLAIN) return *reinterpret_cast<const uint4*>(J.a + (size_t)r * N + n);
+  const size_t row1 = (size_t)(J.L + r) * N;
+  if (J.kind == KS_HMULT) {
+    const uint4 x = *reinterpret_cast<const uint4*>(J.a + row1 + n);
+    const uint4 y = *reinterpret_cast<const uint4*>(J.b + row1 + n);
+    return make_uint4(mulmod(x.x, y.x, m), mulmod(x.y, y.y, m), mulmod(x.z, y.z, m),
+                      mulmod(x.w, y.w, m));
+  }
+  const uint32_t* src = J.a + row1;
+  return make_uint4(src[auto_src(n, J.gal, logN)], src[auto_src(n + 1, J.gal, logN)],
+                    src[auto_src(n + 2, J.gal, logN)], src[auto_src(n + 3, J.gal, logN)]);
+}
+
+// ============================================================================
+// Stage 1: ModUp
+// ============================================================================
+
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const int r = blockIdx.y;
+  if (J.kind == KS_HOIST || r >= J.L) return;
+  __shared__ __align__(16) uint32_t s[kLds];
+  const int logN = K.T.logN;
+  const size_t N = (size_t)1 << logN;
+  const ModC m = ldc(K.T.mod + r);
+  const uint32_t q = m.q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t base = blk0 * 256;
+  const KsView V = ks_view(J, K, N);
+  uint32_t* de = V.de + (size_t)r * N + base;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    const uint4 d = load_d4(J, r, base + e, N, logN, m);
+    lds_blk4_store(s, e, d);
+    if (J.kind != KS_PLAIN) *reinterpret_cast<uint4*>(de + e) = d;
+  }
+  __syncthreads();
+  blk_stages<true>(s, 1 << LOGN1, blk0, K.T.itw + (size_t)r * N, q, q2);
+  __syncthreads();
+  uint32_t* y = V.y + (size_t)r * N + base;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    *reinterpret_cast<uint4*>(y + e) = lds_blk4(s, e);
+  }
+}
+
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const int r = blockIdx.y;
+  if (J.kind == KS_HOIST || r >= J.L) return;
+  __shared__ __align__(16) uint32_t s[kLds];
+  constexpr int C = kTile >> LOGN1;
+  const size_t N = (size_t)1 << K.T.logN;
+  const uint32_t q = ldc(K.T.mod + r).q, q2 = 2 * q;
+  const uint2 sc = ldc(K.modup_scale + (size_t)J.L * K.T.L_max + r);
+  const int col0 = blockIdx.x * C;
+  uint32_t* row = ks_view(J, K, N).y + (size_t)r * N;
+  load_cols<LOGN1>(s, row, col0);
+  __syncthreads();
+  col_stages<LOGN1, true>(s, K.T.itw + (size_t)r * N, q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int lin = (threadIdx.x + kk * kWG) * 4;
+    const int pos = lin / C, c = lin & (C - 1);
+    uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
+    v.x = csub(mul_shoup(v.x, sc.x, sc.y, q), q);
+    v.y = csub(mul_shoup(v.y, sc.x, sc.y, q), q);
+    v.z = csub(mul_shoup(v.z, sc.x, sc.y, q), q);
+    v.w = csub(mul_shoup(v.w, sc.x, sc.y, q), q);
+    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) = v;
+  }
+}
+
+// ModUp BConv of digit j: z[j][r] = sum_i y[j alpha + i] T_{L,j}[r][i] mod prime(r) for every
+// row r outside the digit.  Rows of a block: [g * RB, g * RB + RB); blockIdx.y = j * groups + g.
+// Table columns past a partial digit are zero, so every input load is unconditional.
+template <int ALPHA, int RB>
+__global__ __launch_bounds__(kWG) void k3_bconv_up(KsConst K, JobArg<KsJob> JA, int groups) {
+  const KsJob J = JA.get(blockIdx.z);
+  if (J.kind == KS_HOIST) return;
+  const int j = blockIdx.y / groups, g = blockIdx.y % groups;
+  const size_t N = (size_t)1 << K.T.logN;
+  const KsView V = ks_view(J, K, N);
+  if (j >= V.beta || g * RB >= V.R) return;
+  const int lo = j * ALPHA, hi = min(lo + ALPHA, V.L);
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  uint32_t x[ALPHA];
+#pragma unroll
+  for (int i = 0; i < ALPHA; ++i) x[i] = V.y[(size_t)min(lo + i, V.L - 1) * N + n];
+  const uint32_t* Tt = K.modup_T + ldc(K.modup_T_off + (size_t)V.L * K.beta_max + j);
+  const int r1 = min(g * RB + RB, V.R);
+  for (int r = g * RB; r < r1; ++r) {
+    if (r >= lo && r < hi) continue;
+    const ModC m = ldc(K.T.mod + ks_pidx(r, V.L, K.T.L_max));
+    const uint32_t* t = Tt + (size_t)r * ALPHA;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < ALPHA; ++i) acc += (uint64_t)x[i] * ldc(t + i);
+    V.z[((size_t)j * V.R + r) * N + n] = reduce64(acc, m.q, m.mu_hi, m.mu_lo);
+  }
+}
+
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  if (J.kind == KS_HOIST) return;
+  const size_t N = (size_t)1 << K.T.logN;
+  const KsView V = ks_view(J, K, N);
+  const int gr = blockIdx.y;
+  const int j = gr / V.R, r = gr % V.R;
+  if (j >= V.beta) return;
+  const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
+  if (r >= lo && r < hi) return;
+  __shared__ __align__(16) uint32_t s[kLds];
+  const int pi = ks_pidx(r, V.L, K.T.L_max);
+  const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
+  const int col0 = blockIdx.x * (kTile >> LOGN1);
+  uint32_t* row = V.z + (size_t)gr * N;
+  load_cols<LOGN1>(s, row, col0);
+  __syncthreads();
+  col_stages<LOGN1, false>(s, K.T.tw + (size_t)pi * N, q, q2);
+  __syncthreads();
+  store_cols<LOGN1>(s, row, col0);
+}
+
+// ============================================================================
+// Stage 2: NTT block pass + inner product (+ first INTT pass of ModDown on P rows)
+// ============================================================================
+// HOIST selects the variant for hoisted-rotation jobs (gather of sigma(M), no
+// transform); the other variant serves every other job kind.
+template <int LOGN1, bool HOIST>
+__global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const int logN = K.T.logN;
+  const size_t N = (size_t)1 << logN;
+  const KsView V = ks_view(J, K, N);
+  const int r = blockIdx.y;
+  if (r >= V.R || (J.kind == KS_HOIST) != HOIST) return;
+  __shared__ __align__(16) uint32_t s[kLds];
+  const int pi = ks_pidx(r, V.L, K.T.L_max);
+  const ModC m = ldc(K.T.mod + pi);
+  const uint32_t q = m.q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t base = blk0 * 256;
+  const size_t KR = (size_t)K.T.L_max + K.k;  // key rows
+  uint64_t a0[16], a1[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a0[i] = a1[i] = 0;
+
+  for (int j = 0; j < V.beta; ++j) {
+    const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
+    uint4 v[4];
+    if (HOIST) {
+      // hoisted rotation: sigma_g applied to the shared ModUp rows (a gather)
+      const uint32_t* Mrow = J.b + ((size_t)j * V.R + r) * N;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t n = base + blk_elem(kk);
+        v[kk] = make_uint4(Mrow[auto_src(n, J.gal, logN)], Mrow[auto_src(n + 1, J.gal, logN)],
+                           Mrow[auto_src(n + 2, J.gal, logN)], Mrow[auto_src(n + 3, J.gal, logN)]);
+      }
+    } else if (r >= lo && r < hi) {
+      // digit rows are the switched polynomial itself (kept by K1 unless it is the input)
+      const uint32_t* drow = (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) v[kk] = *reinterpret_cast<const uint4*>(drow + blk_elem(kk));
+    } else {
+      const uint32_t* zrow = V.z + ((size_t)j * V.R + r) * N + base;
+      __syncthreads();  // the previous digit's tile has been read
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int e = blk_elem(kk);
+        lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(zrow + e));
+      }
+      __syncthreads();
+      blk_stages<false>(s, 1 << LOGN1, blk0, K.T.tw + (size_t)pi * N, q, q2);
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) v[kk] = canon4(lds_blk4(s, blk_elem(kk)), q, q2);
+    }
+    const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pi) * N + base;
+    const uint32_t* k1 = k0 + KR * N;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const uint4 e0 = *reinterpret_cast<const uint4*>(k0 + blk_elem(kk));
+      a0[4 * kk + 0] += (uint64_t)v[kk].x * e0.x;
+      a0[4 * kk + 1] += (uint64_t)v[kk].y * e0.y;
+      a0[4 * kk + 2] += (uint64_t)v[kk].z * e0.z;
+      a0[4 * kk + 3] += (uint64_t)v[kk].w * e0.w;
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const uint4 e1 = *reinterpret_cast<const uint4*>(k1 + blk_elem(kk));
+      a1[4 * kk + 0] += (uint64_t)v[kk].x * e1.x;
+      a1[4 * kk + 1] += (uint64_t)v[kk].y * e1.y;
+      a1[4 * kk + 2] += (uint64_t)v[kk].z * e1.z;
+      a1[4 * kk + 3] += (uint64_t)v[kk].w * e1.w;
+    }
+  }
+
+  // one reduction per output (the overflow-free accumulation of Sec. III-C2)
+  uint32_t r0[16], r1[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    r0[i] = reduce64(a0[i], q, m.mu_hi, m.mu_lo);
+    r1[i] = reduce64(a1[i], q, m.mu_hi, m.mu_lo);
+  }
+  uint32_t* acc0 = V.acc + (size_t)r * N + base;
+  uint32_t* acc1 = V.acc + ((size_t)V.R + r) * N + base;
+  if (r < V.L) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int e = blk_elem(kk);
+      *reinterpret_cast<uint4*>(acc0 + e) = make_uint4(r0[4 * kk], r0[4 * kk + 1], r0[4 * kk + 2], r0[4 * kk + 3]);
+      *reinterpret_cast<uint4*>(acc1 + e) = make_uint4(r1[4 * kk], r1[4 * kk + 1], r1[4 * kk + 2], r1[4 * kk + 3]);
+    }
+    return;
+  }
+  // P rows: ModDown starts with an INTT; its block pass runs here on the tile.
+  for (int c = 0; c < 2; ++c) {
+    uint32_t* dst = c ? acc1 : acc0;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const uint32_t* rr = c ? r1 : r0;
+      lds_blk4_store(s, blk_elem(kk), make_uint4(rr[4 * kk], rr[4 * kk + 1], rr[4 * kk + 2], rr[4 * kk + 3]));
+    }
+    __syncthreads();
+    blk_stages<true>(s, 1 << LOGN1, blk0, K.T.itw + (size_t)pi * N, q, q2);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int e = blk_elem(kk);
+      *reinterpret_cast<uint4*>(dst + e) = lds_blk4(s, e);
+    }
+  }
+}
+
+// ============================================================================
+// Stage 3: ModDown of both components
+// ============================================================================
+
+// INTT column pass of the P rows (already through the block pass) -> x [2][k].
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const size_t N = (size_t)1 << K.T.logN;
+  const KsView V = ks_view(J, K, N);
+  const int c = blockIdx.y / K.k, mm = blockIdx.y % K.k;
+  __shared__ __align__(16) uint32_t s[kLds];
+  constexpr int C = kTile >> LOGN1;
+  const int pi = K.T.L_max + mm;
+  const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
+  const uint2 sc = ldc(K.moddown_scale + mm);
+  const int col0 = blockIdx.x * C;
+  load_cols<LOGN1>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
+  __syncthreads();
+  col_stages<LOGN1, true>(s, K.T.itw + (size_t)pi * N, q, q2);
+  __syncthreads();
+  uint32_t* row = V.x + ((size_t)c * K.k + mm) * N;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int lin = (threadIdx.x + kk * kWG) * 4;
+    const int pos = lin / C, cc = lin & (C - 1);
+    uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
+    v.x = csub(mul_shoup(v.x, sc.x, sc.y, q), q);
+    v.y = csub(mul_shoup(v.y, sc.x, sc.y, q), q);
+    v.z = csub(mul_shoup(v.z, sc.x, sc.y, q), q);
+    v.w = csub(mul_shoup(v.w, sc.x, sc.y, q), q);
+    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + cc) = v;
+  }
+}
+
+// w[c][i] = sum_m x[c][m] (P/p_m mod q_i) mod q_i; blockIdx.y = c * groups + g.
+template <int KP, int RB>
+__global__ __launch_bounds__(kWG) void k7_bconv_down(KsConst K, JobArg<KsJob> JA, int groups) {
+  const KsJob J = JA.get(blockIdx.z);
+  const size_t N = (size_t)1 << K.T.logN;
+  const KsView V = ks_view(J, K, N);
+  const int c = blockIdx.y / groups, g = blockIdx.y % groups;
+  if (g * RB >= V.L) return;
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  uint32_t x[KP];
+#pragma unroll
+  for (int mm = 0; mm < KP; ++mm) x[mm] = V.x[((size_t)c * KP + mm) * N + n];
+  const int r1 = min(g * RB + RB, V.L);
+  for (int i = g * RB; i < r1; ++i) {
+    const ModC m = ldc(K.T.mod + i);
+    const uint32_t* t = K.moddown_T + (size_t)i * KP;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int mm = 0; mm < KP; ++mm) acc += (uint64_t)x[mm] * ldc(t + mm);
+    V.w[((size_t)c * V.L + i) * N + n] = reduce64(acc, m.q, m.mu_hi, m.mu_lo);
+  }
+}
+
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const size_t N = (size_t)1 << K.T.logN;
+  const KsView V = ks_view(J, K, N);
+  const int gr = blockIdx.y;
+  if (gr >= 2 * V.L) return;
+  const int i = gr % V.L;
+  __shared__ __align__(16) uint32_t s[kLds];
+  const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
+  const int col0 = blockIdx.x * (kTile >> LOGN1);
+  uint32_t* row = V.w + (size_t)gr * N;
+  load_cols<LOGN1>(s, row, col0);
+  __syncthreads();
+  col_stages<LOGN1, false>(s, K.T.tw + (size_t)i * N, q, q2);
+  __syncthreads();
+  store_cols<LOGN1>(s, row, col0);
+}
+
+// out[c][i] = (acc[c][i] - NTT(w)[c][i]) P^-1 (+ the job's epilogue term).
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const int logN = K.T.logN;
+  const size_t N = (size_t)1 << logN;
+  const KsView V = ks_view(J, K, N);
+  const int gr = blockIdx.y;
+  if (gr >= 2 * V.L) return;
+  const int c = gr / V.L, i = gr % V.L;
+  __shared__ __align__(16) uint32_t s[kLds];
+  const ModC m = ldc(K.T.mod + i);
+  const uint32_t q = m.q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t base = blk0 * 256;
+  const uint32_t* wrow = V.w + (size_t)gr * N + base;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(wrow + e));
+  }
+  __syncthreads();
+  blk_stages<false>(s, 1 << LOGN1, blk0, K.T.tw + (size_t)i * N, q, q2);
+  __syncthreads();
+  const uint2 pv = ldc(K.pinv + i);
+  const uint32_t* accr = V.acc + ((size_t)c * V.R + i) * N + base;
+  uint32_t* out = J.out + ((size_t)c * V.L + i) * N + base;
+  const size_t L = V.L;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    const uint4 w = canon4(lds_blk4(s, e), q, q2);
+    const uint4 a = *reinterpret_cast<const uint4*>(accr + e);
+    uint32_t o[4] = {a.x + q - w.x, a.y + q - w.y, a.z + q - w.z, a.w + q - w.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o[t] = csub(mul_shoup(o[t], pv.x, pv.y, q), q);
+    const uint32_t n = base + e;
+    if (J.kind == KS_HMULT) {
+      // d0 = c0 c0' (c = 0) or d1 = c0 c1' + c1 c0' (c = 1), formed here from the inputs
+      const uint4 x0 = *reinterpret_cast<const uint4*>(J.a + i * N + n);
+      const uint4 y0 = *reinterpret_cast<const uint4*>(J.b + i * N + n);
+      const uint32_t xa[4] = {x0.x, x0.y, x0.z, x0.w}, ya[4] = {y0.x, y0.y, y0.z, y0.w};
+      if (c == 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) o[t] = csub(o[t] + mulmod(xa[t], ya[t], m), q);
+      } else {
+        const uint4 x1 = *reinterpret_cast<const uint4*>(J.a + (L + i) * N + n);
+        const uint4 y1 = *reinterpret_cast<const uint4*>(J.b + (L + i) * N + n);
+        const uint32_t xb[4] = {x1.x, x1.y, x1.z, x1.w}, yb[4] = {y1.x, y1.y, y1.z, y1.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const uint32_t d1 =
+              reduce64((uint64_t)xa[t] * yb[t] + (uint64_t)xb[t] * ya[t], q, m.mu_hi, m.mu_lo);
+          o[t] = csub(o[t] + d1, q);
+        }
+      }
+    } else if ((J.kind == KS_HROT || J.kind == KS_HOIST) && c == 0) {
+      const uint32_t* c0 = J.a + i * N;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o[t] = csub(o[t] + c0[auto_src(n + t, J.gal, logN)], q);
+    }
+    *reinterpret_cast<uint4*>(out + e) = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// ============================================================================
+// Rescale: t = INTT_{q_{L-1}}(a_{L-1}); out_i = (a_i - NTT_{q_i}(t mod q_i)) q_{L-1}^-1
+// Scratch: t [2][N], u [2][L-1][N].
+// ============================================================================
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA) {
+  const RsJob J = JA.get(blockIdx.z);
+  const int c = blockIdx.y, L = J.L, pi = L - 1;
+  __shared__ __align__(16) uint32_t s[kLds];
+  const size_t N = (size_t)1 << K.T.logN;
+  const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t* in = J.a + ((size_t)c * L + pi) * N + blk0 * 256;
+  uint32_t* t = J.ws + (size_t)c * N + blk0 * 256;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
+  }
+  __syncthreads();
+  blk_stages<true>(s, 1 << LOGN1, blk0, K.T.itw + (size_t)pi * N, q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    *reinterpret_cast<uint4*>(t + e) = lds_blk4(s, e);
+  }
+}
+
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
+  const RsJob J = JA.get(blockIdx.z);
+  const int c = blockIdx.y, pi = J.L - 1;
+  __shared__ __align__(16) uint32_t s[kLds];
+  constexpr int C = kTile >> LOGN1;
+  const size_t N = (size_t)1 << K.T.logN;
+  const ModC m = ldc(K.T.mod + pi);
+  const uint32_t q = m.q, q2 = 2 * q;
+  const int col0 = blockIdx.x * C;
+  uint32_t* row = J.ws + (size_t)c * N;
+  load_cols<LOGN1>(s, row, col0);
+  __syncthreads();
+  col_stages<LOGN1, true>(s, K.T.itw + (size_t)pi * N, q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int lin = (threadIdx.x + kk * kWG) * 4;
+    const int pos = lin / C, cc = lin & (C - 1);
+    uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
+    v.x = csub(mul_shoup(v.x, m.ninv, m.ninv_s, q), q);
+    v.y = csub(mul_shoup(v.y, m.ninv, m.ninv_s, q), q);
+    v.z = csub(mul_shoup(v.z, m.ninv, m.ninv_s, q), q);
+    v.w = csub(mul_shoup(v.w, m.ninv, m.ninv_s, q), q);
+    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + cc) = v;
+  }
+}
+
+// NTT column pass of t mod q_i for every i < L - 1 (the broadcast is the loader).
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) {
+  const RsJob J = JA.get(blockIdx.z);
+  const int L1 = J.L - 1;
+  const int gr = blockIdx.y;
+  if (gr >= 2 * L1) return;
+  const int c = gr / L1, i = gr % L1;
+  __shared__ __align__(16) uint32_t s[kLds];
+  constexpr int C = kTile >> LOGN1;
+  const size_t N = (size_t)1 << K.T.logN;
+  const ModC m = ldc(K.T.mod + i);
+  const uint32_t q = m.q, q2 = 2 * q;
+  const int col0 = blockIdx.x * C;
+  const uint32_t* t = J.ws + (size_t)c * N;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int lin = (threadIdx.x + kk * kWG) * 4;
+    const int pos = lin / C, cc = lin & (C - 1);
+    uint4 v = *reinterpret_cast<const uint4*>(t + pos * 256 + col0 + cc);
+    v.x = reduce32(v.x, q, m.mu32);
+    v.y = reduce32(v.y, q, m.mu32);
+    v.z = reduce32(v.z, q, m.mu32);
+    v.w = reduce32(v.w, q, m.mu32);
+    *reinterpret_cast<uint4*>(s + lidx_col(pos, cc, C)) = v;
+  }
+  __syncthreads();
+  col_stages<LOGN1, false>(s, K.T.tw + (size_t)i * N, q, q2);
+  __syncthreads();
+  store_cols<LOGN1>(s, J.ws + (size_t)(2 + gr) * N, col0);
+}
+
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJob> JA) {
+  const RsJob J = JA.get(blockIdx.z);
+  const int L1 = J.L - 1;
+  const int gr = blockIdx.y;
+  if (gr >= 2 * L1) return;
+  const int c = gr / L1, i = gr % L1;
+  __shared__ __align__(16) uint32_t s[kLds];
+  const size_t N = (size_t)1 << K.T.logN;
+  const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t base = blk0 * 256;
+  const uint32_t* u = J.ws + (size_t)(2 + gr) * N + base;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(u + e));
+  }
+  __syncthreads();
+  blk_stages<false>(s, 1 << LOGN1, blk0, K.T.tw + (size_t)i * N, q, q2);
+  __syncthreads();
+  const uint2 qi = ldc(K.rescale_inv + (size_t)J.L * K.T.L_max + i);
+  const uint32_t* a = J.a + ((size_t)c * J.L + i) * N + base;
+  uint32_t* out = J.out + ((size_t)c * L1 + i) * N + base;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    const uint4 v = canon4(lds_blk4(s, e), q, q2);
+    const uint4 x = *reinterpret_cast<const uint4*>(a + e);
+    *reinterpret_cast<uint4*>(out + e) =
+        make_uint4(csub(mul_shoup(x.x + q - v.x, qi.x, qi.y, q), q), csub(mul_shoup(x.y + q - v.y, qi.x, qi.y, q), q),
+                   csub(mul_shoup(x.z + q - v.z, qi.x, qi.y, q), q), csub(mul_shoup(x.w + q - v.w, qi.x, qi.y, q), q));
+  }
+}
+
+}  // namespace
+
+size_t ks_ws_words(const Ctx& c, int L) {
+  const size_t R = (size_t)L + c.k;
+  return ks_hoist_ws_words(c, L) + (2 * (size_t)L + (size_t)c.beta(L) * R) * c.N;
+}
+
+size_t ks_hoist_ws_words(const Ctx& c, int L) {
+  return (2 * ((size_t)L + c.k) + 2 * (size_t)c.k + 2 * (size_t)L) * c.N;
+}
+
+size_t rs_ws_words(const Ctx& c, int L) { return (2 + 2 * (size_t)L) * c.N; }
+
+namespace {
+constexpr int kRB = 4;  // BConv output rows per work-group
+
+template <int A>
+hipError_t launch_k3(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int groups) {
+  k3_bconv_up<A, kRB><<<g, kWG, 0, st>>>(K, J, groups);
+  return hipSuccess;
+}
+template <int KP>
+hipError_t launch_k7(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int groups) {
+  k7_bconv_down<KP, kRB><<<g, kWG, 0, st>>>(K, J, groups);
+  return hipSuccess;
+}
+
+// Dispatch a small compile-time count (digit size or special-prime count, 1..16).
+template <int A>
+struct K3 {
+  static hipError_t run(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int gr) {
+    return launch_k3<A>(g, st, K, J, gr);
+  }
+};
+template <int A>
+struct K7 {
+  static hipError_t run(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int gr) {
+    return launch_k7<A>(g, st, K, J, gr);
+  }
+};
+
+template <template <int> class F, int V>
+hipError_t small_dispatch(int v, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
+                          int gr) {
+  if constexpr (V > kMaxAlpha) {
+    return hipErrorInvalidValue;
+  } else {
+    if (v == V) return F<V>::run(g, st, K, J, gr);
+    return small_dispatch<F, V + 1>(v, g, st, K, J, gr);
+  }
+}
+
+template <int L1>
+hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs, int njobs,
+                       int Lmax, bool with_modup, bool with_hoist, hipStream_t st) {
+  const int Rmax = Lmax + c.k;
+  const int tiles = c.N / kTile;
+  const int cols = c.N / kWG;
+  const int bmax = c.beta(Lmax);
+  const int up_groups = (Rmax + kRB - 1) / kRB;
+  const int down_groups = (Lmax + kRB - 1) / kRB;
+  hipError_t e;
+  if (with_modup) {
+    k1_intt_blks<L1><<<dim3(tiles, Lmax, njobs), kWG, 0, st>>>(K, jobs);
+    k2_intt_cols<L1><<<dim3(tiles, Lmax, njobs), kWG, 0, st>>>(K, jobs);
+    e = small_dispatch<K3, 1>(c.alpha, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
+    if (e != hipSuccess) return e;
+    k4_ntt_cols<L1><<<dim3(tiles, bmax * Rmax, njobs), kWG, 0, st>>>(K, jobs);
+  }
+  if (with_modup) k5_ntt_blks_ip<L1, false><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
+  if (with_hoist) k5_ntt_blks_ip<L1, true><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
+  k6_intt_cols_p<L1><<<dim3(tiles, 2 * c.k, njobs), kWG, 0, st>>>(K, jobs);
+  e = small_dispatch<K7, 1>(c.k, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
+  if (e != hipSuccess) return e;
+  k8_ntt_cols_w<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
+  k9_ntt_blks_combine<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
+  return hipGetLastError();
+}
+
+template <int L1>
+hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs, int njobs,
+                       int Lmax, hipStream_t st) {
+  const int tiles = c.N / kTile;
+  r1_intt_blks<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
+  r2_intt_cols<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
+  r3_ntt_cols<L1><<<dim3(tiles, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
+  r4_ntt_blks_combine<L1><<<dim3(tiles, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t ks_launch(const Ctx& c, const JobArg<KsJob>& jobs, int njobs, int Lmax, bool with_modup,
+                     bool with_hoist, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  const KsConst K = make_const(c);
+  switch (c.logN - kBlockLog) {
+    case 4: return ks_launch_t<4>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
+    case 5: return ks_launch_t<5>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
+    case 6: return ks_launch_t<6>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
+    case 7: return ks_launch_t<7>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
+    case 8: return ks_launch_t<8>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t rs_launch(const Ctx& c, const JobArg<RsJob>& jobs, int njobs, int Lmax, hipStream_t st) {
+  if (njobs <= 0 || Lmax < 2) return hipSuccess;
+  const KsConst K = make_const(c);
+  switch (c.logN - kBlockLog) {
+    case 4: return rs_launch_t<4>(c, K, jobs, njobs, Lmax, st);
+    case 5: return rs_launch_t<5>(c, K, jobs, njobs, Lmax, st);
+    case 6: return rs_launch_t<6>(c, K, jobs, njobs, Lmax, st);
+    case 7: return rs_launch_t<7>(c, K, jobs, njobs, Lmax, st);
+    case 8: return rs_launch_t<8>(c, K, jobs, njobs, Lmax, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ckks

@@ -1,0 +1,197 @@
+// Device-side building blocks of the two-pass NTT over LDS tiles (shared by
+// kernels.hip and keyswitch.hip).
+//
+// A limb of N = N1 * 256 words is viewed as N1 rows of 256.  The column pass
+// runs the first log2(N1) Cooley-Tukey stages on columns j + 256 r (r < N1);
+// a work-group tile holds C = 4096 / N1 adjacent columns.  The block pass runs
+// the last 8 stages inside contiguous 256-word blocks; a tile holds 16 blocks.
+// Inside a tile the stages run as radix-16 register phases (16 elements per
+// thread, four stages per LDS round trip) with lazy Shoup butterflies.  The
+// twiddle of butterfly group (m, i) is psi^brv(m + i) (inverse: psi^-brv(m + i)).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "arith.h"
+#include "ctx.h"
+
+namespace ckks {
+
+constexpr int kLds = 4352;  // padded tile: 4096 + 256 words (both layouts)
+
+__device__ __forceinline__ int lidx_col(int pos, int c, int C) { return pos * C + c + ((pos >> 4) << 4); }
+__device__ __forceinline__ int lidx_blk(int line, int pos) { return line * 272 + pos + (pos >> 4); }
+
+// ----- column-pass phases (stages on pos bits [blo, blo + LOGR)) -----------
+template <int LOGR, bool INV>
+__device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo,
+                                          const uint2* __restrict__ tw, uint32_t q, uint32_t q2) {
+  constexpr int R = 1 << LOGR;
+  constexpr int GPT = 16 / R;
+#pragma unroll
+  for (int gg = 0; gg < GPT; ++gg) {
+    const int g = threadIdx.x + gg * kWG;
+    const int c = g & (C - 1);
+    const int rest = g / C;
+    const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
+    uint32_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = s[lidx_col(base | (j << blo), c, C)];
+    if (!INV) {
+#pragma unroll
+      for (int kb = LOGR - 1; kb >= 0; --kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(1 << (logN1 - 1 - beta)) | (pos >> (beta + 1))];
+          bfly_ct(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < LOGR; ++kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(1 << (logN1 - 1 - beta)) | (pos >> (beta + 1))];
+          bfly_gs(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) s[lidx_col(base | (j << blo), c, C)] = v[j];
+  }
+}
+
+// ----- block-pass phases (16 lines of 256; stages on pos bits [blo, blo + LOGR)) ---
+template <int LOGR, bool INV>
+__device__ __forceinline__ void blk_phase(uint32_t* s, int N1, int blk0, int blo,
+                                          const uint2* __restrict__ tw, uint32_t q, uint32_t q2) {
+  constexpr int R = 1 << LOGR;
+  constexpr int GPT = 16 / R;
+  constexpr int NB = 8 - LOGR;
+#pragma unroll
+  for (int gg = 0; gg < GPT; ++gg) {
+    const int g = threadIdx.x + gg * kWG;
+    const int rest = g & ((1 << NB) - 1);
+    const int line = g >> NB;
+    const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
+    const int lb = N1 + blk0 + line;
+    uint32_t v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = s[lidx_blk(line, base | (j << blo))];
+    if (!INV) {
+#pragma unroll
+      for (int kb = LOGR - 1; kb >= 0; --kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(lb << (7 - beta)) | (pos >> (beta + 1))];
+          bfly_ct(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < LOGR; ++kb) {
+        const int beta = blo + kb;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j & (1 << kb)) continue;
+          const int pos = base | (j << blo);
+          const uint2 W = tw[(lb << (7 - beta)) | (pos >> (beta + 1))];
+          bfly_gs(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) s[lidx_blk(line, base | (j << blo))] = v[j];
+  }
+}
+
+// All column stages of one tile, forward (high bits first) or inverse (low bits first).
+template <int LOGN1, bool INV>
+__device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
+  constexpr int C = kTile >> LOGN1;
+  constexpr int REM = LOGN1 - 4;  // 0..4
+  if (!INV) {
+    col_phase<4, false>(s, LOGN1, C, REM, tw, q, q2);
+    if constexpr (REM > 0) {
+      __syncthreads();
+      col_phase<(REM > 0 ? REM : 1), false>(s, LOGN1, C, 0, tw, q, q2);
+    }
+  } else {
+    col_phase<4, true>(s, LOGN1, C, 0, tw, q, q2);
+    if constexpr (REM > 0) {
+      __syncthreads();
+      col_phase<(REM > 0 ? REM : 1), true>(s, LOGN1, C, 4, tw, q, q2);
+    }
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ void blk_stages(uint32_t* s, int N1, int blk0, const uint2* tw,
+                                           uint32_t q, uint32_t q2) {
+  if (!INV) {
+    blk_phase<4, false>(s, N1, blk0, 4, tw, q, q2);
+    __syncthreads();
+    blk_phase<4, false>(s, N1, blk0, 0, tw, q, q2);
+  } else {
+    blk_phase<4, true>(s, N1, blk0, 0, tw, q, q2);
+    __syncthreads();
+    blk_phase<4, true>(s, N1, blk0, 4, tw, q, q2);
+  }
+}
+
+// ----- tile load / store helpers --------------------------------------------
+template <int LOGN1>
+__device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restrict__ row, int col0) {
+  constexpr int C = kTile >> LOGN1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lin = (threadIdx.x + k * kWG) * 4;
+    const int pos = lin / C, c = lin & (C - 1);
+    const uint4 v = *reinterpret_cast<const uint4*>(row + pos * 256 + col0 + c);
+    *reinterpret_cast<uint4*>(s + lidx_col(pos, c, C)) = v;
+  }
+}
+
+template <int LOGN1>
+__device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restrict__ row, int col0) {
+  constexpr int C = kTile >> LOGN1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lin = (threadIdx.x + k * kWG) * 4;
+    const int pos = lin / C, c = lin & (C - 1);
+    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) =
+        *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
+  }
+}
+
+// Block tiles: element e of the tile (e < 4096) is line e >> 8, pos e & 255.
+// Thread t owns tile elements 4t + 1024k .. +3 (k < 4) in the load/store/epilogue loops.
+__device__ __forceinline__ int blk_elem(int k) { return (threadIdx.x + k * kWG) * 4; }
+// (The block layout's 1-in-16 padding breaks 16-byte alignment, so these
+// LDS accesses stay 32-bit.)
+__device__ __forceinline__ uint4 lds_blk4(const uint32_t* s, int e) {
+  const uint32_t* p = s + lidx_blk(e >> 8, e & 255);  // 4 | e: no pad inside the quad
+  return make_uint4(p[0], p[1], p[2], p[3]);
+}
+__device__ __forceinline__ void lds_blk4_store(uint32_t* s, int e, uint4 v) {
+  uint32_t* p = s + lidx_blk(e >> 8, e & 255);
+  p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
+}
+
+__device__ __forceinline__ uint4 canon4(uint4 v, uint32_t q, uint32_t q2) {
+  v.x = csub(csub(v.x, q2), q);
+  v.y = csub(csub(v.y, q2), q);
+  v.z = csub(csub(v.z, q2), q);
+  v.w = csub(csub(v.w, q2), q);
+  return v;
+}
+
+}  // namespace ckks

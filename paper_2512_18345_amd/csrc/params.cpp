@@ -212,6 +212,8 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
   if (!(err = upload(&c.d_itw, itw, code)).empty()) return err;
   if (!(err = upload(&c.d_modup_scale, mscale, code)).empty()) return err;
   if (!(err = upload(&c.d_modup_T, mT, code)).empty()) return err;
+  std::vector<uint32_t> toff(c.modup_T_off.begin(), c.modup_T_off.end());
+  if (!(err = upload(&c.d_modup_T_off, toff, code)).empty()) return err;
   if (!(err = upload(&c.d_moddown_scale, dscale, code)).empty()) return err;
   if (!(err = upload(&c.d_moddown_T, dT, code)).empty()) return err;
   if (!(err = upload(&c.d_pinv, pinv, code)).empty()) return err;
@@ -221,7 +223,7 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
 }
 
 void free_tables(Ctx& c) {
-  void* ptrs[] = {c.d_mod, c.d_tw, c.d_itw, c.d_modup_scale, c.d_modup_T,
+  void* ptrs[] = {c.d_mod, c.d_tw, c.d_itw, c.d_modup_scale, c.d_modup_T, c.d_modup_T_off,
                   c.d_moddown_scale, c.d_moddown_T, c.d_pinv, c.d_rescale_inv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
