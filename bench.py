@@ -32,14 +32,34 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--latency-reps", type=int, default=200)
-    ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (for scaling HBM counters)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib: int):
+    """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+    give the factor between counter units and bytes moved."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 3}), flush=True)
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(batch-level data parallelism across GPUs needs no collective and is not run here).",
@@ -83,11 +103,17 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # Dominant kernel: NTT block pass fused with the key inner product (stage 2
+    # of key-switching), timed by events around each of its launches on the
+    # stream it runs on, inside the timed region.
+    ip_launches = 2 * args.steps
+    P.ckks_trace_begin(h, P.STAGE["NTT_IP"], ip_launches)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    ip_ms = P.ckks_trace_end(h, ip_launches)
     ks_per_step = 2
     value = ks_per_step * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
@@ -104,26 +130,16 @@ def main():
         lat.append(e0.elapsed_time(e1) * 1e3)
     lat = np.array(lat)
 
-    # Dominant kernel: the evaluation-key inner product (stage 2), one kernel per call.
     beta = ctx.beta(L)
     R = L + k
-    M = torch.randint(0, 2 ** 29, (beta, R, N), dtype=torch.int32, device="cuda")
-    acc = torch.empty((2, R, N), dtype=torch.int32, device="cuda")
-    for _ in range(3):
-        P.ckks_inner_product(h, M, L, d_rlk, acc, stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
-        P.ckks_inner_product(h, M, L, d_rlk, acc, stream)
-    e1.record(stream)
-    e1.synchronize()
-    ip_us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
     limb = N * LIMB_BYTES
-    ip_bytes = (beta * R + 2 * beta * R + 2 * R) * limb  # read M and the key rows, write acc
+    # per launch: the beta*R ModUp rows in, the 2*beta*R key rows in, the 2*R
+    # accumulator rows out
+    ip_bytes = (3 * beta + 2) * R * limb
+    ip_us = 1e3 * float(np.mean(ip_ms))
     achieved = ip_bytes / (ip_us * 1e-6) / 1e9
     roofline = {
-        "kernel": "k_inner_product",
+        "kernel": "k5_ntt_blks_ip",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": 8000.0,
@@ -131,8 +147,13 @@ def main():
         "frac": round(achieved / 8000.0, 4),
         "traffic": None,
         "avg_us": round(ip_us, 2),
+        "launches": len(ip_ms),
         "bytes_per_launch": ip_bytes,
     }
+
+    batched = None
+    if not args.no_batched:
+        batched = batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, args.batch_reps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -156,11 +177,74 @@ def main():
         "hmult_latency_us": {"p50": round(float(np.percentile(lat, 50)), 2),
                              "p99": round(float(np.percentile(lat, 99)), 2),
                              "reps": int(len(lat))},
+        "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
+
+
+def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
+    """Batched key-switches/s on the same GPU: (a) 8 HMults at L=36, one
+    batch (one captured graph) vs 8 single calls; (b) the 64-job mixed-level
+    batch (levels uniform in 4..36; HMult 0.4, HRot 0.4 over 8 rotation keys,
+    rescale 0.2) as one captured graph."""
+    import torch
+    N, L = spec.N, spec.L_max
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n_ks):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return n_ks * reps / (time.perf_counter() - t0)
+
+    # (a) same work, batched vs single-op
+    outs = [torch.empty((2, L, N), dtype=torch.int32, device="cuda") for _ in range(8)]
+    ws = ctx.workspace("HMULT", L)
+    single = timed(lambda: [P.ckks_hmult(ctx.handle, d_ct1, d_ct2, L, d_rlk, o, ws, stream) for o in outs], 8)
+    b8 = P.ckks_batch_create(ctx.handle, [dict(op=P.JOB["HMULT"], L=L, in0=d_ct1, in1=d_ct2, key=d_rlk,
+                                               out=o) for o in outs], use_graph=True)
+    batched8 = timed(lambda: P.ckks_batch_launch(b8, stream), 8)
+    P.ckks_batch_destroy(b8)
+    del outs, ws
+
+    # (b) the 64-job mixed batch
+    rng = ci.Rng(3)
+    keys = [dev(rng.evk(spec)) for _ in range(9)]  # 8 rotation keys + the relinearisation key
+    jobs, n_ks, keep = [], 0, []
+    for _ in range(64):
+        Lj = int(rng.integers(4, 37))
+        u = float(rng.integers(0, 10)) / 10.0
+        a = dev(rng.polys(2, spec.q[:Lj], N))
+        keep.append(a)
+        if u < 0.4:
+            b = dev(rng.polys(2, spec.q[:Lj], N))
+            keep.append(b)
+            o = torch.empty((2, Lj, N), dtype=torch.int32, device="cuda")
+            jobs.append(dict(op=P.JOB["HMULT"], L=Lj, in0=a, in1=b, key=keys[8], out=o))
+            n_ks += 1
+        elif u < 0.8:
+            o = torch.empty((2, Lj, N), dtype=torch.int32, device="cuda")
+            r = int(rng.integers(0, 8))
+            jobs.append(dict(op=P.JOB["HROT"], L=Lj, rot=1 + r, in0=a, key=keys[r], out=o))
+            n_ks += 1
+        else:
+            o = torch.empty((2, Lj - 1, N), dtype=torch.int32, device="cuda")
+            jobs.append(dict(op=P.JOB["RESCALE"], L=Lj, in0=a, out=o))
+        keep.append(o)
+    b64 = P.ckks_batch_create(ctx.handle, jobs, use_graph=True)
+    mixed = timed(lambda: P.ckks_batch_launch(b64, stream), n_ks)
+    P.ckks_batch_destroy(b64)
+    return {"hmult_L36_x8": {"single_op_ks_per_s": round(single, 1),
+                             "batched_graph_ks_per_s": round(batched8, 1),
+                             "speedup": round(batched8 / single, 3)},
+            "mixed_64_jobs_L4_36": {"ks_per_s": round(mixed, 1), "key_switches": n_ks,
+                                    "jobs": 64, "graph": True}}
 
 
 def cpu_baseline(spec, ct1, ct2, ctr, rot, rlk, rotk, budget_s):

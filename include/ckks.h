@@ -70,6 +70,20 @@ enum {
     CKKS_OP_HROT_HOISTED = 7
 };
 
+/* Pipeline stages that can be timed with ckks_trace_begin / ckks_trace_end. */
+enum {
+    CKKS_STAGE_INTT_BLOCKS = 1,     /* K1: INTT block pass of the switched polynomial */
+    CKKS_STAGE_INTT_COLS = 2,       /* K2: INTT column pass + BConv pre-multiply */
+    CKKS_STAGE_BCONV_UP = 3,        /* K3: ModUp base conversion, all digits */
+    CKKS_STAGE_NTT_COLS_UP = 4,     /* K4: NTT column pass of the ModUp rows */
+    CKKS_STAGE_NTT_IP = 5,          /* K5: NTT block pass + key inner product (+ P-row INTT pass) */
+    CKKS_STAGE_INTT_COLS_P = 6,     /* K6: INTT column pass of the P rows */
+    CKKS_STAGE_BCONV_DOWN = 7,      /* K7: ModDown base conversion */
+    CKKS_STAGE_NTT_COLS_DOWN = 8,   /* K8: NTT column pass of the ModDown rows */
+    CKKS_STAGE_NTT_COMBINE = 9,     /* K9: NTT block pass + (acc - w) P^-1 + epilogue */
+    CKKS_STAGE_RESCALE_NTT = 10     /* R4: rescale NTT block pass + combine */
+};
+
 typedef struct ckks_ctx ckks_ctx;
 
 /* Thread-local description of the last error on this thread ("" if none). */
@@ -194,6 +208,63 @@ int ckks_hrot_hoisted(const ckks_ctx *ctx, const uint32_t *ct, int L, const int 
  */
 int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, void *ws,
                  size_t ws_bytes, void *stream);
+
+/*
+ * Batches (Sec. IV-A batching; Sec. IV-C one submission per static graph).
+ * A batch is a fixed list of independent jobs, each at its own level, run
+ * together: every pipeline kernel covers all jobs of the batch at once
+ * (nine kernels for all key-switching jobs, four for all rescale jobs), and
+ * with use_graph != 0 the whole launch sequence is captured once into a
+ * hipGraph at creation, so ckks_batch_launch is a single graph submission.
+ * Each job's result is bitwise the result of the corresponding single call.
+ */
+enum {
+    CKKS_JOB_KEYSWITCH = 0,  /* in0 = d [L][N]; out = KS(d) [2][L][N] */
+    CKKS_JOB_HMULT = 1,      /* in0 = ct1, in1 = ct2; out = HMult [2][L][N] */
+    CKKS_JOB_HROT = 2,       /* in0 = ct; out = HRot by rot [2][L][N] */
+    CKKS_JOB_RESCALE = 3     /* in0 = ct; out = rescale [2][L-1][N]; key unused */
+};
+
+typedef struct ckks_job {
+    int op;               /* CKKS_JOB_* */
+    int L;                /* level of the job (>= 2 for RESCALE) */
+    int rot;              /* rotation for CKKS_JOB_HROT */
+    int reserved;
+    const uint32_t *in0;  /* device pointers, as in the single-call entry points */
+    const uint32_t *in1;
+    const uint32_t *key;
+    uint32_t *out;
+} ckks_job;
+
+typedef struct ckks_batch ckks_batch;
+
+/*
+ * Build a batch of n jobs (host array, copied).  Allocates the batch's
+ * device job tables and scratch (held until ckks_batch_destroy) and, with
+ * use_graph, captures the launches.  Data pointers are not read here; they
+ * must be valid whenever the batch is launched, and outputs must not alias
+ * each other or any input.  Errors: CKKS_EINVAL, CKKS_ENOMEM, CKKS_EHIP.
+ */
+int ckks_batch_create(const ckks_ctx *ctx, const ckks_job *h_jobs, int n, int use_graph,
+                      ckks_batch **out);
+/* Enqueue the whole batch on `stream` (asynchronous). */
+int ckks_batch_launch(ckks_batch *batch, void *stream);
+/* Device bytes the batch holds (tables + scratch). */
+size_t ckks_batch_device_bytes(const ckks_batch *batch);
+int ckks_batch_destroy(ckks_batch *batch);
+
+/*
+ * Kernel tracing.  Between ckks_trace_begin and ckks_trace_end, every launch
+ * of pipeline stage `stage` (CKKS_STAGE_*) by this context is bracketed by a
+ * pair of HIP events recorded on the launch's own stream, for the first
+ * `capacity` launches.  ckks_trace_end waits for the last recorded event,
+ * writes the per-launch durations in milliseconds to h_ms (capacity floats,
+ * may be NULL) and the number of recorded launches to *count, and disarms.
+ * The events are created in ckks_trace_begin and destroyed in ckks_trace_end.
+ * Not for concurrent use from several host threads on one context.
+ */
+int ckks_trace_begin(ckks_ctx *ctx, int stage, int capacity);
+int ckks_trace_end(ckks_ctx *ctx, float *h_ms, int *count);
 
 #ifdef __cplusplus
 }

@@ -17,19 +17,33 @@ __all__ = [
     "ckks_ctx_create", "ckks_ctx_destroy", "ckks_workspace_bytes",
     "ckks_ntt", "ckks_intt", "ckks_automorph", "ckks_tensor", "ckks_modup",
     "ckks_inner_product", "ckks_moddown", "ckks_keyswitch", "ckks_hmult",
-    "ckks_hrot", "ckks_hrot_hoisted", "ckks_rescale",
+    "ckks_hrot", "ckks_hrot_hoisted", "ckks_rescale", "ckks_trace_begin", "ckks_trace_end", "STAGE",
+    "JOB", "ckks_job", "ckks_batch_create", "ckks_batch_launch", "ckks_batch_device_bytes",
+    "ckks_batch_destroy",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libckks.so")
 
 OP = dict(NTT=0, MODUP=1, MODDOWN=2, KEYSWITCH=3, HMULT=4, HROT=5, RESCALE=6, HROT_HOISTED=7)
+STAGE = dict(INTT_BLOCKS=1, INTT_COLS=2, BCONV_UP=3, NTT_COLS_UP=4, NTT_IP=5, INTT_COLS_P=6,
+             BCONV_DOWN=7, NTT_COLS_DOWN=8, NTT_COMBINE=9, RESCALE_NTT=10)
 
 
 class CkksError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"ckks error {code}: {msg}")
         self.code = code
+
+
+JOB = dict(KEYSWITCH=0, HMULT=1, HROT=2, RESCALE=3)
+
+
+class ckks_job(ctypes.Structure):
+    """Mirror of struct ckks_job (include/ckks.h)."""
+    _fields_ = [("op", ctypes.c_int), ("L", ctypes.c_int), ("rot", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("in0", ctypes.c_void_p), ("in1", ctypes.c_void_p),
+                ("key", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -52,6 +66,11 @@ _SIGS = {
     "ckks_hrot": [_vp, _vp, _i, _i, _vp, _vp, _vp, _sz, _vp],
     "ckks_hrot_hoisted": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp],
     "ckks_rescale": [_vp, _vp, _i, _vp, _vp, _sz, _vp],
+    "ckks_trace_begin": [_vp, _i, _i],
+    "ckks_batch_create": [_vp, _vp, _i, _i, ctypes.POINTER(_vp)],
+    "ckks_batch_launch": [_vp, _vp],
+    "ckks_batch_destroy": [_vp],
+    "ckks_trace_end": [_vp, _vp, ctypes.POINTER(_i)],
 }
 
 
@@ -70,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.ckks_last_error.argtypes = []
         L.ckks_workspace_bytes.restype = _sz
         L.ckks_workspace_bytes.argtypes = [_vp, _i, _i]
+        L.ckks_batch_device_bytes.restype = _sz
+        L.ckks_batch_device_bytes.argtypes = [_vp]
         _lib = L
     return _lib
 
@@ -185,6 +206,45 @@ def ckks_hrot_hoisted(ctx, ct, L, rots, rotks, outs, ws=None, stream=None):
 def ckks_rescale(ctx, ct, L, out, ws=None, stream=None):
     w, nb = _ws(ws)
     _check(lib().ckks_rescale(ctx, _ptr(ct), L, _ptr(out), w, nb, _stream(stream)))
+
+
+def ckks_batch_create(ctx, jobs, use_graph=True) -> int:
+    """jobs: sequence of dicts or ckks_job; tensors are taken by device address."""
+    arr = (ckks_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        if isinstance(j, ckks_job):
+            arr[i] = j
+        else:
+            arr[i] = ckks_job(int(j["op"]), int(j["L"]), int(j.get("rot", 0)), 0,
+                              _ptr(j["in0"]), _ptr(j.get("in1")), _ptr(j.get("key")), _ptr(j["out"]))
+    h = _vp()
+    _check(lib().ckks_batch_create(ctx, ctypes.cast(arr, _vp), len(jobs), int(bool(use_graph)),
+                                   ctypes.byref(h)))
+    return h.value
+
+
+def ckks_batch_launch(batch, stream=None):
+    _check(lib().ckks_batch_launch(batch, _stream(stream)))
+
+
+def ckks_batch_device_bytes(batch) -> int:
+    return int(lib().ckks_batch_device_bytes(batch))
+
+
+def ckks_batch_destroy(batch):
+    _check(lib().ckks_batch_destroy(batch))
+
+
+def ckks_trace_begin(ctx, stage, capacity):
+    _check(lib().ckks_trace_begin(ctx, int(stage), int(capacity)))
+
+
+def ckks_trace_end(ctx, capacity):
+    """Returns the per-launch durations (ms) recorded since ckks_trace_begin."""
+    buf = (ctypes.c_float * max(int(capacity), 1))()
+    n = _i(0)
+    _check(lib().ckks_trace_end(ctx, ctypes.cast(buf, _vp), ctypes.byref(n)))
+    return [float(buf[i]) for i in range(n.value)]
 
 
 class Context:

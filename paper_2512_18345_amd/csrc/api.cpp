@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ctx.h"
 #include "keyswitch.h"
@@ -161,6 +162,42 @@ int run_one(const Ctx& c, int kind, int L, uint32_t gal, const uint32_t* a, cons
   ja.inl[0] = KsJob{kind, L, gal, 0, a, b, key, out, (uint32_t*)ws};
   CKKS_TRY(ks_launch(c, ja, 1, L, true, false, st), "key-switching pipeline");
   return CKKS_OK;
+}
+
+}  // namespace
+
+struct ckks_batch {
+  const Ctx* c = nullptr;
+  int n_ks = 0, n_rs = 0, Lmax_ks = 0, Lmax_rs = 0;
+  KsJob* d_ks = nullptr;
+  RsJob* d_rs = nullptr;
+  void* d_ws = nullptr;
+  size_t bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;
+};
+
+namespace {
+
+hipError_t batch_enqueue(ckks_batch* b, hipStream_t st) {
+  JobArg<KsJob> ka{};
+  ka.table = b->d_ks;
+  hipError_t e = ks_launch(*b->c, ka, b->n_ks, b->Lmax_ks, true, false, st);
+  if (e != hipSuccess) return e;
+  JobArg<RsJob> ra{};
+  ra.table = b->d_rs;
+  return rs_launch(*b->c, ra, b->n_rs, b->Lmax_rs, st);
+}
+
+void batch_free(ckks_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  if (b->d_ks) (void)hipFree(b->d_ks);
+  if (b->d_rs) (void)hipFree(b->d_rs);
+  if (b->d_ws) (void)hipFree(b->d_ws);
+  delete b;
 }
 
 }  // namespace
@@ -381,6 +418,146 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int L, uint32_t* out, 
   ja.inl[0] = RsJob{L, {0, 0, 0}, ct, out, (uint32_t*)ws, nullptr};
   CKKS_TRY(rs_launch(c, ja, 1, L, (hipStream_t)stream), "rescale");
   return CKKS_OK;
+}
+
+int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int use_graph,
+                      ckks_batch** out) {
+  if (!ctx || !h_jobs || !out || n < 1 || n > 65535) return fail(CKKS_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  const Ctx& c = ctx->c;
+  std::vector<KsJob> ks;
+  std::vector<RsJob> rs;
+  std::vector<size_t> ks_off, rs_off;
+  size_t ws = 0;
+  int Lks = 0, Lrs = 0;
+  for (int i = 0; i < n; ++i) {
+    const ckks_job& j = h_jobs[i];
+    const int lo = j.op == CKKS_JOB_RESCALE ? 2 : 1;
+    if (j.L < lo || j.L > c.L_max || !j.in0 || !j.out)
+      return fail(CKKS_EINVAL, "job " + std::to_string(i) + ": bad level or null pointer");
+    if (j.op == CKKS_JOB_RESCALE) {
+      rs.push_back(RsJob{j.L, {0, 0, 0}, j.in0, j.out, nullptr, nullptr});
+      rs_off.push_back(ws);
+      ws += round_up(rs_ws_words(c, j.L) * 4);
+      Lrs = std::max(Lrs, j.L);
+    } else if (j.op == CKKS_JOB_KEYSWITCH || j.op == CKKS_JOB_HMULT || j.op == CKKS_JOB_HROT) {
+      if (!j.key || (j.op == CKKS_JOB_HMULT && !j.in1))
+        return fail(CKKS_EINVAL, "job " + std::to_string(i) + ": null key or second input");
+      const int kind = j.op == CKKS_JOB_KEYSWITCH ? KS_PLAIN : j.op == CKKS_JOB_HMULT ? KS_HMULT : KS_HROT;
+      ks.push_back(KsJob{kind, j.L, j.op == CKKS_JOB_HROT ? galois(c, j.rot) : 0u, 0, j.in0,
+                         j.op == CKKS_JOB_HMULT ? j.in1 : nullptr, j.key, j.out, nullptr});
+      ks_off.push_back(ws);
+      ws += round_up(ks_ws_words(c, j.L) * 4);
+      Lks = std::max(Lks, j.L);
+    } else {
+      return fail(CKKS_EINVAL, "job " + std::to_string(i) + ": unknown op");
+    }
+  }
+  DeviceGuard g(c.device);
+  ckks_batch* b = new (std::nothrow) ckks_batch;
+  if (!b) return fail(CKKS_ENOMEM, "host allocation failed");
+  b->c = &c;
+  b->n_ks = (int)ks.size();
+  b->n_rs = (int)rs.size();
+  b->Lmax_ks = Lks;
+  b->Lmax_rs = Lrs;
+  const size_t tab = round_up(sizeof(KsJob) * ks.size()) + round_up(sizeof(RsJob) * rs.size());
+  if (hipMalloc(&b->d_ws, ws) != hipSuccess ||
+      (!ks.empty() && hipMalloc(&b->d_ks, sizeof(KsJob) * ks.size()) != hipSuccess) ||
+      (!rs.empty() && hipMalloc(&b->d_rs, sizeof(RsJob) * rs.size()) != hipSuccess)) {
+    batch_free(b);
+    return fail(CKKS_ENOMEM, "device allocation for the batch failed");
+  }
+  b->bytes = ws + tab;
+  for (size_t i = 0; i < ks.size(); ++i) ks[i].ws = (uint32_t*)((char*)b->d_ws + ks_off[i]);
+  for (size_t i = 0; i < rs.size(); ++i) rs[i].ws = (uint32_t*)((char*)b->d_ws + rs_off[i]);
+  if ((!ks.empty() && hipMemcpy(b->d_ks, ks.data(), sizeof(KsJob) * ks.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+      (!rs.empty() && hipMemcpy(b->d_rs, rs.data(), sizeof(RsJob) * rs.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+    batch_free(b);
+    return fail(CKKS_EHIP, "copying the job table failed");
+  }
+  if (use_graph) {
+    hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t le = batch_enqueue(b, b->capture);
+      e = hipStreamEndCapture(b->capture, &b->graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      batch_free(b);
+      return hip_fail(e, "capturing the batch graph");
+    }
+  }
+  *out = b;
+  return CKKS_OK;
+}
+
+int ckks_batch_launch(ckks_batch* b, void* stream) {
+  if (!b) return fail(CKKS_EINVAL, "null batch");
+  DeviceGuard g(b->c->device);
+  const hipStream_t st = (hipStream_t)stream;
+  if (b->exec)
+    CKKS_TRY(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
+  else
+    CKKS_TRY(batch_enqueue(b, st), "batch launch");
+  return CKKS_OK;
+}
+
+size_t ckks_batch_device_bytes(const ckks_batch* b) { return b ? b->bytes : 0; }
+
+int ckks_batch_destroy(ckks_batch* b) {
+  if (!b) return CKKS_OK;
+  DeviceGuard g(b->c->device);
+  batch_free(b);
+  return CKKS_OK;
+}
+
+int ckks_trace_begin(ckks_ctx* ctx, int stage, int capacity) {
+  if (!ctx) return fail(CKKS_EINVAL, "null context");
+  if (stage < CKKS_STAGE_INTT_BLOCKS || stage > CKKS_STAGE_RESCALE_NTT || capacity < 1)
+    return fail(CKKS_EINVAL, "bad trace stage or capacity");
+  Ctx& c = ctx->c;
+  if (c.trace.stage) return fail(CKKS_EINVAL, "a trace is already armed on this context");
+  DeviceGuard g(c.device);
+  c.trace.starts.assign(capacity, nullptr);
+  c.trace.stops.assign(capacity, nullptr);
+  for (int i = 0; i < capacity; ++i) {
+    if (hipEventCreate(&c.trace.starts[i]) != hipSuccess ||
+        hipEventCreate(&c.trace.stops[i]) != hipSuccess) {
+      for (auto* v : {&c.trace.starts, &c.trace.stops})
+        for (hipEvent_t ev : *v)
+          if (ev) (void)hipEventDestroy(ev);
+      c.trace = Ctx::Trace{};
+      return fail(CKKS_EHIP, "hipEventCreate failed");
+    }
+  }
+  c.trace.count = 0;
+  c.trace.stage = stage;
+  return CKKS_OK;
+}
+
+int ckks_trace_end(ckks_ctx* ctx, float* h_ms, int* count) {
+  if (!ctx) return fail(CKKS_EINVAL, "null context");
+  Ctx& c = ctx->c;
+  if (!c.trace.stage) return fail(CKKS_EINVAL, "no trace armed");
+  DeviceGuard g(c.device);
+  int rc = CKKS_OK;
+  const int n = c.trace.count;
+  if (n > 0 && hipEventSynchronize(c.trace.stops[n - 1]) != hipSuccess) rc = fail(CKKS_EHIP, "event sync failed");
+  for (int i = 0; i < n && rc == CKKS_OK; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c.trace.starts[i], c.trace.stops[i]) != hipSuccess)
+      rc = fail(CKKS_EHIP, "hipEventElapsedTime failed");
+    else if (h_ms)
+      h_ms[i] = ms;
+  }
+  if (count) *count = n;
+  for (auto* v : {&c.trace.starts, &c.trace.stops})
+    for (hipEvent_t ev : *v) (void)hipEventDestroy(ev);
+  c.trace = Ctx::Trace{};
+  return rc;
 }
 
 }  // extern "C"

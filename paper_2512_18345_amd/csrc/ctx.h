@@ -27,13 +27,37 @@ struct ModC {
   uint32_t ninv, ninv_s;  // N^-1 mod q and its Shoup companion
 };
 
-// What a kernel needs to find a prime's tables.
+// What a kernel needs to find a prime's tables.  Every twiddle is stored as
+// (w, floor(w 2^32 / q)).
+//  * column pass: tw / itw [nprimes][N1], index m + i < N1 -> psi^(+-brv_logN(m + i));
+//  * block pass (after the twist below the 256-word block transform is the same
+//    for every block): ctw / ictw [nprimes][256], index 2^s + g ->
+//    psi^(+-(N / 2^s) brv_s(g));
+//  * twist of block b: twist / itwist [nprimes][N1][32], entries j < 16 are
+//    rho_b^(+-j) and 16 + h are rho_b^(+-16 h), rho_b = psi^(2 brv_logN1(b) + 1);
+//    the block pass multiplies element j of block b by rho_b^j before the
+//    forward network (by rho_b^-j after the inverse one).
 struct DevTab {
   const ModC* mod;   // [nprimes]
-  const uint2* tw;   // [nprimes][N]: (psi^brv(i), Shoup) at index i in [1, N)
-  const uint2* itw;  // [nprimes][N]: (psi^-brv(i), Shoup)
+  const uint2* tw;
+  const uint2* itw;
+  const uint2* ctw;
+  const uint2* ictw;
+  const uint2* twist;
+  const uint2* itwist;
   int logN;
   int L_max;
+  __host__ __device__ int logN1() const { return logN - 8; }
+  __device__ const uint2* col_tw(int pi) const { return tw + ((size_t)pi << logN1()); }
+  __device__ const uint2* col_itw(int pi) const { return itw + ((size_t)pi << logN1()); }
+  __device__ const uint2* blk_tw(int pi) const { return ctw + ((size_t)pi << 8); }
+  __device__ const uint2* blk_itw(int pi) const { return ictw + ((size_t)pi << 8); }
+  __device__ const uint2* blk_twist(int pi, int b) const {
+    return twist + ((((size_t)pi << logN1()) + b) << 5);
+  }
+  __device__ const uint2* blk_itwist(int pi, int b) const {
+    return itwist + ((((size_t)pi << logN1()) + b) << 5);
+  }
 };
 
 // Rows of a launch: row r of the data is prime index pidx(r).
@@ -53,8 +77,12 @@ struct Ctx {
 
   // device tables
   ModC* d_mod = nullptr;
-  uint2* d_tw = nullptr;
+  uint2* d_tw = nullptr;      // [nprimes][N1]
   uint2* d_itw = nullptr;
+  uint2* d_ctw = nullptr;     // [nprimes][256]
+  uint2* d_ictw = nullptr;
+  uint2* d_twist = nullptr;   // [nprimes][N1][32]
+  uint2* d_itwist = nullptr;
   // ModUp at level L (1-based): per Q row i < L, (N^-1 * (D_j/q_i)^-1, Shoup) where j = i / alpha.
   uint2* d_modup_scale = nullptr;     // [L_max + 1][L_max]
   // ModUp BConv tables at level L, digit j: T[r][i] = (D_j / q_{j alpha + i}) mod prime(r),
@@ -70,7 +98,26 @@ struct Ctx {
   // Rescale at level L: q_{L-1}^-1 mod q_i (Shoup), i < L - 1.
   uint2* d_rescale_inv = nullptr;     // [L_max + 1][L_max]
 
-  DevTab tab() const { return DevTab{d_mod, d_tw, d_itw, logN, L_max}; }
+  // kernel tracing (ckks_trace_begin / ckks_trace_end)
+  struct Trace {
+    int stage = 0;
+    std::vector<hipEvent_t> starts, stops;
+    int count = 0;
+  };
+  mutable Trace trace;
+  // Record the start / stop event of a traced stage around a launch.
+  void trace_pre(int stage, hipStream_t st) const {
+    if (trace.stage == stage && trace.count < (int)trace.starts.size())
+      (void)hipEventRecord(trace.starts[trace.count], st);
+  }
+  void trace_post(int stage, hipStream_t st) const {
+    if (trace.stage == stage && trace.count < (int)trace.starts.size())
+      (void)hipEventRecord(trace.stops[trace.count++], st);
+  }
+
+  DevTab tab() const {
+    return DevTab{d_mod, d_tw, d_itw, d_ctw, d_ictw, d_twist, d_itwist, logN, L_max};
+  }
   RowMap rows(int L) const { return RowMap{L, L_max}; }
   int beta(int L) const { return (L + alpha - 1) / alpha; }
   int beta_max() const { return beta(L_max); }

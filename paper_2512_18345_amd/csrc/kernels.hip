@@ -25,11 +25,11 @@ __global__ __launch_bounds__(kWG) void k_ntt_cols(DevTab T, RowMap rm, const uin
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   const size_t N = (size_t)1 << T.logN;
-  const uint32_t q = T.mod[pi].q, q2 = 2 * q;
+  const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int col0 = blockIdx.x * (kTile >> LOGN1);
   load_cols<LOGN1>(s, src + r * N, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, T.tw + pi * N, q, q2);
+  col_stages<LOGN1, false>(s, T.col_tw(pi), q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, dst + r * N, col0);
 }
@@ -43,17 +43,18 @@ __global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uin
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   const size_t N = (size_t)1 << T.logN;
-  const uint32_t q = T.mod[pi].q, q2 = 2 * q;
+  const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
   const uint32_t* in = src + r * N + blk0 * 256;
   uint32_t* out = dst + r * N + blk0 * 256;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = blk_elem(k);
-    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
+    lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(in + e),
+                                T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, 1 << LOGN1, blk0, T.tw + pi * N, q, q2);
+  blk_stages<false>(s, T.blk_tw(pi), q, q2);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const ui
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   const size_t N = (size_t)1 << T.logN;
-  const uint32_t q = T.mod[pi].q, q2 = 2 * q;
+  const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
   const uint32_t* in = src + r * N + blk0 * 256;
   uint32_t* out = dst + r * N + blk0 * 256;
@@ -81,12 +82,13 @@ __global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const ui
     lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
   }
   __syncthreads();
-  blk_stages<true>(s, 1 << LOGN1, blk0, T.itw + pi * N, q, q2);
+  blk_stages<true>(s, T.blk_itw(pi), q, q2);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = blk_elem(k);
-    *reinterpret_cast<uint4*>(out + e) = lds_blk4(s, e);
+    *reinterpret_cast<uint4*>(out + e) =
+        twist4(lds_blk4(s, e), T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q);
   }
 }
 
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const ui
   const int col0 = blockIdx.x * C;
   load_cols<LOGN1>(s, src + r * N, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, T.itw + pi * N, q, q2);
+  col_stages<LOGN1, true>(s, T.col_itw(pi), q, q2);
   __syncthreads();
   uint32_t* row = dst + r * N;
 #pragma unroll

@@ -128,13 +128,14 @@ __global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA)
     if (J.kind != KS_PLAIN) *reinterpret_cast<uint4*>(de + e) = d;
   }
   __syncthreads();
-  blk_stages<true>(s, 1 << LOGN1, blk0, K.T.itw + (size_t)r * N, q, q2);
+  blk_stages<true>(s, K.T.blk_itw(r), q, q2);
   __syncthreads();
   uint32_t* y = V.y + (size_t)r * N + base;
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    *reinterpret_cast<uint4*>(y + e) = lds_blk4(s, e);
+    *reinterpret_cast<uint4*>(y + e) =
+        twist4(lds_blk4(s, e), K.T.blk_itwist(r, blk0 + (e >> 8)), e & 255, q);
   }
 }
 
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA)
   uint32_t* row = ks_view(J, K, N).y + (size_t)r * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, K.T.itw + (size_t)r * N, q, q2);
+  col_stages<LOGN1, true>(s, K.T.col_itw(r), q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kWG) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) 
   uint32_t* row = V.z + (size_t)gr * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, K.T.tw + (size_t)pi * N, q, q2);
+  col_stages<LOGN1, false>(s, K.T.col_tw(pi), q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, row, col0);
 }
@@ -266,10 +267,11 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int e = blk_elem(kk);
-        lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(zrow + e));
+        lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(zrow + e),
+                                    K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
       }
       __syncthreads();
-      blk_stages<false>(s, 1 << LOGN1, blk0, K.T.tw + (size_t)pi * N, q, q2);
+      blk_stages<false>(s, K.T.blk_tw(pi), q, q2);
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) v[kk] = canon4(lds_blk4(s, blk_elem(kk)), q, q2);
@@ -322,12 +324,13 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
       lds_blk4_store(s, blk_elem(kk), make_uint4(rr[4 * kk], rr[4 * kk + 1], rr[4 * kk + 2], rr[4 * kk + 3]));
     }
     __syncthreads();
-    blk_stages<true>(s, 1 << LOGN1, blk0, K.T.itw + (size_t)pi * N, q, q2);
+    blk_stages<true>(s, K.T.blk_itw(pi), q, q2);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int e = blk_elem(kk);
-      *reinterpret_cast<uint4*>(dst + e) = lds_blk4(s, e);
+      *reinterpret_cast<uint4*>(dst + e) =
+          twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q);
     }
   }
 }
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> J
   const int col0 = blockIdx.x * C;
   load_cols<LOGN1>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, K.T.itw + (size_t)pi * N, q, q2);
+  col_stages<LOGN1, true>(s, K.T.col_itw(pi), q, q2);
   __syncthreads();
   uint32_t* row = V.x + ((size_t)c * K.k + mm) * N;
 #pragma unroll
@@ -404,7 +407,7 @@ __global__ __launch_bounds__(kWG) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA
   uint32_t* row = V.w + (size_t)gr * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, K.T.tw + (size_t)i * N, q, q2);
+  col_stages<LOGN1, false>(s, K.T.col_tw(i), q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, row, col0);
 }
@@ -428,10 +431,11 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(wrow + e));
+    lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(wrow + e),
+                                K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, 1 << LOGN1, blk0, K.T.tw + (size_t)i * N, q, q2);
+  blk_stages<false>(s, K.T.blk_tw(i), q, q2);
   __syncthreads();
   const uint2 pv = ldc(K.pinv + i);
   const uint32_t* accr = V.acc + ((size_t)c * V.R + i) * N + base;
@@ -494,12 +498,13 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
     lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
   }
   __syncthreads();
-  blk_stages<true>(s, 1 << LOGN1, blk0, K.T.itw + (size_t)pi * N, q, q2);
+  blk_stages<true>(s, K.T.blk_itw(pi), q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    *reinterpret_cast<uint4*>(t + e) = lds_blk4(s, e);
+    *reinterpret_cast<uint4*>(t + e) =
+        twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q);
   }
 }
 
@@ -516,7 +521,7 @@ __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA)
   uint32_t* row = J.ws + (size_t)c * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, K.T.itw + (size_t)pi * N, q, q2);
+  col_stages<LOGN1, true>(s, K.T.col_itw(pi), q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) 
     *reinterpret_cast<uint4*>(s + lidx_col(pos, cc, C)) = v;
   }
   __syncthreads();
-  col_stages<LOGN1, false>(s, K.T.tw + (size_t)i * N, q, q2);
+  col_stages<LOGN1, false>(s, K.T.col_tw(i), q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, J.ws + (size_t)(2 + gr) * N, col0);
 }
@@ -579,10 +584,11 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(u + e));
+    lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(u + e),
+                                K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, 1 << LOGN1, blk0, K.T.tw + (size_t)i * N, q, q2);
+  blk_stages<false>(s, K.T.blk_tw(i), q, q2);
   __syncthreads();
   const uint2 qi = ldc(K.rescale_inv + (size_t)J.L * K.T.L_max + i);
   const uint32_t* a = J.a + ((size_t)c * J.L + i) * N + base;
@@ -661,19 +667,37 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   const int down_groups = (Lmax + kRB - 1) / kRB;
   hipError_t e;
   if (with_modup) {
+    c.trace_pre(CKKS_STAGE_INTT_BLOCKS, st);
     k1_intt_blks<L1><<<dim3(tiles, Lmax, njobs), kWG, 0, st>>>(K, jobs);
+    c.trace_post(CKKS_STAGE_INTT_BLOCKS, st);
+    c.trace_pre(CKKS_STAGE_INTT_COLS, st);
     k2_intt_cols<L1><<<dim3(tiles, Lmax, njobs), kWG, 0, st>>>(K, jobs);
+    c.trace_post(CKKS_STAGE_INTT_COLS, st);
+    c.trace_pre(CKKS_STAGE_BCONV_UP, st);
     e = small_dispatch<K3, 1>(c.alpha, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
+    c.trace_post(CKKS_STAGE_BCONV_UP, st);
     if (e != hipSuccess) return e;
+    c.trace_pre(CKKS_STAGE_NTT_COLS_UP, st);
     k4_ntt_cols<L1><<<dim3(tiles, bmax * Rmax, njobs), kWG, 0, st>>>(K, jobs);
+    c.trace_post(CKKS_STAGE_NTT_COLS_UP, st);
+    c.trace_pre(CKKS_STAGE_NTT_IP, st);
+    k5_ntt_blks_ip<L1, false><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
+    c.trace_post(CKKS_STAGE_NTT_IP, st);
   }
-  if (with_modup) k5_ntt_blks_ip<L1, false><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
   if (with_hoist) k5_ntt_blks_ip<L1, true><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
+  c.trace_pre(CKKS_STAGE_INTT_COLS_P, st);
   k6_intt_cols_p<L1><<<dim3(tiles, 2 * c.k, njobs), kWG, 0, st>>>(K, jobs);
+  c.trace_post(CKKS_STAGE_INTT_COLS_P, st);
+  c.trace_pre(CKKS_STAGE_BCONV_DOWN, st);
   e = small_dispatch<K7, 1>(c.k, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
+  c.trace_post(CKKS_STAGE_BCONV_DOWN, st);
   if (e != hipSuccess) return e;
+  c.trace_pre(CKKS_STAGE_NTT_COLS_DOWN, st);
   k8_ntt_cols_w<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
+  c.trace_post(CKKS_STAGE_NTT_COLS_DOWN, st);
+  c.trace_pre(CKKS_STAGE_NTT_COMBINE, st);
   k9_ntt_blks_combine<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
+  c.trace_post(CKKS_STAGE_NTT_COMBINE, st);
   return hipGetLastError();
 }
 
@@ -684,7 +708,9 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
   r1_intt_blks<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
   r2_intt_cols<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
   r3_ntt_cols<L1><<<dim3(tiles, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
+  c.trace_pre(CKKS_STAGE_RESCALE_NTT, st);
   r4_ntt_blks_combine<L1><<<dim3(tiles, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
+  c.trace_post(CKKS_STAGE_RESCALE_NTT, st);
   return hipGetLastError();
 }
 }  // namespace

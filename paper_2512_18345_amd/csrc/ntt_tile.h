@@ -67,9 +67,12 @@ __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo
 }
 
 // ----- block-pass phases (16 lines of 256; stages on pos bits [blo, blo + LOGR)) ---
+// After the twist the 256-word block transform is the same for every block:
+// the pair on pos bit beta uses ctw[(1 << (7 - beta)) | (pos >> (beta + 1))],
+// and its stage on bit 7 (first forward / last inverse) multiplies by 1.
 template <int LOGR, bool INV>
-__device__ __forceinline__ void blk_phase(uint32_t* s, int N1, int blk0, int blo,
-                                          const uint2* __restrict__ tw, uint32_t q, uint32_t q2) {
+__device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const uint2* __restrict__ tw,
+                                          uint32_t q, uint32_t q2) {
   constexpr int R = 1 << LOGR;
   constexpr int GPT = 16 / R;
   constexpr int NB = 8 - LOGR;
@@ -79,7 +82,6 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int N1, int blk0, int blo
     const int rest = g & ((1 << NB) - 1);
     const int line = g >> NB;
     const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
-    const int lb = N1 + blk0 + line;
     uint32_t v[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) v[j] = s[lidx_blk(line, base | (j << blo))];
@@ -90,9 +92,15 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int N1, int blk0, int blo
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           if (j & (1 << kb)) continue;
-          const int pos = base | (j << blo);
-          const uint2 W = tw[(lb << (7 - beta)) | (pos >> (beta + 1))];
-          bfly_ct(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+          if (beta == 7) {
+            const uint32_t xx = csub(v[j], q2), yy = csub(v[j | (1 << kb)], q2);
+            v[j] = xx + yy;
+            v[j | (1 << kb)] = xx + q2 - yy;
+          } else {
+            const int pos = base | (j << blo);
+            const uint2 W = tw[(1 << (7 - beta)) | (pos >> (beta + 1))];
+            bfly_ct(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+          }
         }
       }
     } else {
@@ -102,9 +110,15 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int N1, int blk0, int blo
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           if (j & (1 << kb)) continue;
-          const int pos = base | (j << blo);
-          const uint2 W = tw[(lb << (7 - beta)) | (pos >> (beta + 1))];
-          bfly_gs(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+          if (beta == 7) {
+            const uint32_t x = v[j], y = v[j | (1 << kb)];
+            v[j] = csub(x + y, q2);
+            v[j | (1 << kb)] = csub(x + q2 - y, q2);
+          } else {
+            const int pos = base | (j << blo);
+            const uint2 W = tw[(1 << (7 - beta)) | (pos >> (beta + 1))];
+            bfly_gs(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
+          }
         }
       }
     }
@@ -134,17 +148,30 @@ __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_
 }
 
 template <bool INV>
-__device__ __forceinline__ void blk_stages(uint32_t* s, int N1, int blk0, const uint2* tw,
-                                           uint32_t q, uint32_t q2) {
+__device__ __forceinline__ void blk_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
   if (!INV) {
-    blk_phase<4, false>(s, N1, blk0, 4, tw, q, q2);
+    blk_phase<4, false>(s, 4, tw, q, q2);
     __syncthreads();
-    blk_phase<4, false>(s, N1, blk0, 0, tw, q, q2);
+    blk_phase<4, false>(s, 0, tw, q, q2);
   } else {
-    blk_phase<4, true>(s, N1, blk0, 0, tw, q, q2);
+    blk_phase<4, true>(s, 0, tw, q, q2);
     __syncthreads();
-    blk_phase<4, true>(s, N1, blk0, 4, tw, q, q2);
+    blk_phase<4, true>(s, 4, tw, q, q2);
   }
+}
+
+// Multiply the quad at block position pos (4 | pos) by rho^pos .. rho^(pos+3),
+// tb = the block's 32-entry twist table (rho^j for j < 16, rho^(16 h) at 16 + h).
+// Any input below 2^32; output in [0, 2q).
+__device__ __forceinline__ uint4 twist4(uint4 v, const uint2* __restrict__ tb, int pos, uint32_t q) {
+  const uint2 hi = tb[16 + (pos >> 4)];
+  const uint2* lo = tb + (pos & 15);
+  const uint2 l0 = lo[0], l1 = lo[1], l2 = lo[2], l3 = lo[3];
+  v.x = mul_shoup(mul_shoup(v.x, l0.x, l0.y, q), hi.x, hi.y, q);
+  v.y = mul_shoup(mul_shoup(v.y, l1.x, l1.y, q), hi.x, hi.y, q);
+  v.z = mul_shoup(mul_shoup(v.z, l2.x, l2.y, q), hi.x, hi.y, q);
+  v.w = mul_shoup(mul_shoup(v.w, l3.x, l3.y, q), hi.x, hi.y, q);
+  return v;
 }
 
 // ----- tile load / store helpers --------------------------------------------

@@ -1,5 +1,5 @@
 // Host-side construction of a context's tables: twiddles (Sec. II-B1), the
-// base-conversion tables T[i][j] = (Q*/Q_j) mod P_i with their pre-multiply
+// base-conversion tables T[i][j] = (Q^* / Q_j) mod P_i with their pre-multiply
 // constants (Sec. II-B2, III-C2) for every level and digit, the ModDown and
 // rescale constants.  All host arithmetic is exact (unsigned __int128 where a
 // product can exceed 64 bits).
@@ -104,9 +104,12 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
   }
 
   // per-prime constants and twiddle tables
+  const u64 N1 = N >> 8;
+  const int logN1 = c.logN - 8;
   std::vector<ModC> mod(nP);
-  std::vector<uint2> tw((size_t)nP * N), itw((size_t)nP * N);
-  std::vector<u64> pw(N), pwi(N);
+  std::vector<uint2> tw((size_t)nP * N1), itw((size_t)nP * N1);
+  std::vector<uint2> ctw((size_t)nP * 256), ictw((size_t)nP * 256);
+  std::vector<uint2> twist((size_t)nP * N1 * 32), itwist((size_t)nP * N1 * 32);
   for (int i = 0; i < nP; ++i) {
     const u64 qi = c.primes[i];
     const u64 psi = min_root(qi, N), psii = invm(psi, qi);
@@ -115,15 +118,32 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
     const uint2 ns = shoup(ninv, qi);
     mod[i] = ModC{(uint32_t)qi, (uint32_t)((1ull << 32) / qi), (uint32_t)(mu64 >> 32),
                   (uint32_t)mu64, ns.x, ns.y};
-    pw[0] = pwi[0] = 1;
-    for (u64 e = 1; e < N; ++e) {
-      pw[e] = mulm(pw[e - 1], psi, qi);
-      pwi[e] = mulm(pwi[e - 1], psii, qi);
-    }
-    for (u64 e = 0; e < N; ++e) {
+    // column pass: the first N1 entries of the bit-reversed table
+    for (u64 e = 0; e < N1; ++e) {
       const uint32_t b = brv((uint32_t)e, c.logN);
-      tw[(size_t)i * N + e] = shoup(pw[b], qi);
-      itw[(size_t)i * N + e] = shoup(pwi[b], qi);
+      tw[(size_t)i * N1 + e] = shoup(powm(psi, b, qi), qi);
+      itw[(size_t)i * N1 + e] = shoup(powm(psii, b, qi), qi);
+    }
+    // block pass (twisted): index 2^s + g -> psi^((N / 2^s) brv_s(g))
+    ctw[(size_t)i * 256] = ictw[(size_t)i * 256] = shoup(1, qi);
+    for (int s = 0; s < 8; ++s)
+      for (u64 g = 0; g < (1ull << s); ++g) {
+        const u64 ex = (N >> s) * (s ? brv((uint32_t)g, s) : 0);
+        ctw[(size_t)i * 256 + (1u << s) + g] = shoup(powm(psi, ex, qi), qi);
+        ictw[(size_t)i * 256 + (1u << s) + g] = shoup(powm(psii, ex, qi), qi);
+      }
+    // twist of block b: rho_b = psi^(2 brv(b) + 1)
+    for (u64 b = 0; b < N1; ++b) {
+      const u64 rho = powm(psi, 2 * (u64)brv((uint32_t)b, logN1) + 1, qi);
+      const u64 rhoi = invm(rho, qi);
+      uint2* t = &twist[((size_t)i * N1 + b) * 32];
+      uint2* ti = &itwist[((size_t)i * N1 + b) * 32];
+      for (u64 j = 0; j < 16; ++j) {
+        t[j] = shoup(powm(rho, j, qi), qi);
+        ti[j] = shoup(powm(rhoi, j, qi), qi);
+        t[16 + j] = shoup(powm(rho, 16 * j, qi), qi);
+        ti[16 + j] = shoup(powm(rhoi, 16 * j, qi), qi);
+      }
     }
   }
   c.h_mod = mod;
@@ -210,6 +230,10 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
   if (!(err = upload(&c.d_mod, mod, code)).empty()) return err;
   if (!(err = upload(&c.d_tw, tw, code)).empty()) return err;
   if (!(err = upload(&c.d_itw, itw, code)).empty()) return err;
+  if (!(err = upload(&c.d_ctw, ctw, code)).empty()) return err;
+  if (!(err = upload(&c.d_ictw, ictw, code)).empty()) return err;
+  if (!(err = upload(&c.d_twist, twist, code)).empty()) return err;
+  if (!(err = upload(&c.d_itwist, itwist, code)).empty()) return err;
   if (!(err = upload(&c.d_modup_scale, mscale, code)).empty()) return err;
   if (!(err = upload(&c.d_modup_T, mT, code)).empty()) return err;
   std::vector<uint32_t> toff(c.modup_T_off.begin(), c.modup_T_off.end());
@@ -223,7 +247,7 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
 }
 
 void free_tables(Ctx& c) {
-  void* ptrs[] = {c.d_mod, c.d_tw, c.d_itw, c.d_modup_scale, c.d_modup_T, c.d_modup_T_off,
+  void* ptrs[] = {c.d_mod, c.d_tw, c.d_itw, c.d_ctw, c.d_ictw, c.d_twist, c.d_itwist, c.d_modup_scale, c.d_modup_T, c.d_modup_T_off,
                   c.d_moddown_scale, c.d_moddown_T, c.d_pinv, c.d_rescale_inv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

@@ -1,0 +1,103 @@
+"""Batched execution (one job table per launch, optionally one hipGraph per
+batch): every job's result must be bitwise the result of the corresponding
+single call, for uneven levels and mixed operations, on repeated launches."""
+import numpy as np
+import pytest
+import torch
+
+import ckks_inputs as ci
+import oracle as O
+import paper_2512_18345_amd as P
+from gpu_helpers import dev, empty, first_mismatch, host
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def _make_jobs(spec, ctx, rng, n, levels, keys):
+    jobs, singles = [], []
+    N = spec.N
+    for i in range(n):
+        op = ["HMULT", "HROT", "RESCALE", "KEYSWITCH"][i % 4]
+        L = int(levels[i])
+        if op == "RESCALE":
+            L = max(L, 2)
+        ct1 = dev(rng.polys(2, spec.q[:L], N))
+        ct2 = dev(rng.polys(2, spec.q[:L], N))
+        key = keys[i % len(keys)]
+        rot = rng.rotation(N)
+        if op == "RESCALE":
+            out = empty(2, L - 1, N)
+            jobs.append(dict(op=P.JOB[op], L=L, in0=ct1, out=out))
+        elif op == "KEYSWITCH":
+            out = empty(2, L, N)
+            jobs.append(dict(op=P.JOB[op], L=L, in0=ct1[0].contiguous(), key=key, out=out))
+        else:
+            out = empty(2, L, N)
+            jobs.append(dict(op=P.JOB[op], L=L, rot=rot, in0=ct1, in1=ct2 if op == "HMULT" else None,
+                             key=key, out=out))
+        singles.append((op, L, rot, ct1, ct2, key))
+    return jobs, singles
+
+
+def _single(ctx, op, L, rot, ct1, ct2, key):
+    h, N = ctx.handle, ctx.N
+    if op == "RESCALE":
+        out = empty(2, L - 1, N)
+        P.ckks_rescale(h, ct1, L, out, ctx.workspace("RESCALE", L))
+    elif op == "KEYSWITCH":
+        out = empty(2, L, N)
+        P.ckks_keyswitch(h, ct1[0].contiguous(), L, key, out, ctx.workspace("KEYSWITCH", L))
+    elif op == "HMULT":
+        out = empty(2, L, N)
+        P.ckks_hmult(h, ct1, ct2, L, key, out, ctx.workspace("HMULT", L))
+    else:
+        out = empty(2, L, N)
+        P.ckks_hrot(h, ct1, L, rot, key, out, ctx.workspace("HROT", L))
+    return host(out)
+
+
+@pytest.mark.parametrize("name,n,use_graph", [("n12_l4", 9, True), ("n16_l36", 12, True),
+                                               ("n16_l36", 6, False)])
+def test_batch_equals_single_calls(name, n, use_graph):
+    spec = ci.get(name)
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(spec.seed + 100)
+    keys = [dev(rng.evk(spec)) for _ in range(2)]
+    levels = rng.integers(1, spec.L_max + 1, n)
+    jobs, singles = _make_jobs(spec, ctx, rng, n, levels, keys)
+    b = P.ckks_batch_create(ctx.handle, jobs, use_graph=use_graph)
+    try:
+        want = [_single(ctx, *s) for s in singles]
+        for rep in range(3):  # graph replays with eager work and syncs in between
+            for j in jobs:
+                j["out"].fill_(-1)
+            P.ckks_batch_launch(b)
+            torch.cuda.synchronize()
+            for i, j in enumerate(jobs):
+                msg = first_mismatch(host(j["out"]), want[i])
+                assert not msg, f"replay {rep}, job {i} ({singles[i][0]}, L={singles[i][1]}): {msg}"
+            _ = _single(ctx, *singles[0])
+    finally:
+        P.ckks_batch_destroy(b)
+
+
+def test_batch_job_against_oracle():
+    """One batched HMult at a partial-digit level checked against the oracle too."""
+    spec = ci.get("n16_l36")
+    ctx = P.Context.from_spec(spec)
+    par = O.Params.from_spec(spec)
+    rng = ci.Rng(77)
+    L = 17
+    ct1 = rng.polys(2, spec.q[:L], spec.N)
+    ct2 = rng.polys(2, spec.q[:L], spec.N)
+    key = rng.evk(spec)
+    out = empty(2, L, spec.N)
+    b = P.ckks_batch_create(ctx.handle, [dict(op=P.JOB["HMULT"], L=L, in0=dev(ct1), in1=dev(ct2),
+                                              key=dev(key), out=out)])
+    try:
+        P.ckks_batch_launch(b)
+        msg = first_mismatch(host(out), O.hmult(par, ct1, ct2, L, key))
+        assert not msg, msg
+    finally:
+        P.ckks_batch_destroy(b)
