@@ -36,6 +36,12 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--boot-trace", action="store_true",
+                    help="only run the bootstrapping-shaped operation trace (132 key-switches)")
+    ap.add_argument("--serve", action="store_true",
+                    help="only run the serving-loop benchmark (Poisson arrivals, p50/p99)")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling HBM counters)")
     return ap.parse_args()
@@ -59,6 +65,12 @@ def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.serve:
+        serve_bench(args)
+        return
+    if args.boot_trace:
+        boot_trace_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -245,6 +257,132 @@ def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
                              "speedup": round(batched8 / single, 3)},
             "mixed_64_jobs_L4_36": {"ks_per_s": round(mixed, 1), "key_switches": n_ks,
                                     "jobs": 64, "graph": True}}
+
+
+def boot_trace_bench(args):
+    """The bootstrapping-shaped trace at N=2^16 from L=36: one run to warm up,
+    then --steps timed runs; reports ms per trace and key-switches/s."""
+    import torch
+    import ckks_inputs as ci
+    import paper_2512_18345_amd as P
+    from paper_2512_18345_amd import trace
+    torch.cuda.set_device(0)
+    spec = ci.get("boot_trace_n16")
+    shape = ci.BOOT_TRACE
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(spec.seed)
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32).copy()).cuda()
+
+    ct = dev(rng.polys(2, spec.q, spec.N))
+    rots = sorted(set(shape["baby"]) | set(shape["giant"]))
+    keys = {r: dev(rng.evk(spec)) for r in rots}
+    rlk = dev(rng.evk(spec))
+    pts = [dev(rng.residues(spec.q, spec.N)) for _ in range(len(shape["baby"]) * len(shape["giant"]))]
+    stream = torch.cuda.current_stream()
+    trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, Lf = trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts, stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    nks = trace.key_switches(shape)
+    print(json.dumps({"boot_trace": {"ms_per_trace": round(dt * 1e3, 3), "key_switches": nks,
+                                     "ks_per_s": round(nks / dt, 1), "L_start": spec.L_max, "L_end": Lf,
+                                     "runs": args.steps}}), flush=True)
+
+
+def serve_bench(args):
+    """Serving loop under Poisson arrivals.  A request is b ~ U{1..32} jobs
+    (key-switch or HMult, equally likely) at one N in {2^15, 2^16} and one level
+    L ~ U{2..36}; request latency = last job's completion - arrival.  First a
+    closed-loop flood measures the saturated job rate; then arrivals at 0.5,
+    0.8 and 0.95 of it."""
+    import random
+    import torch
+    import ckks_inputs as ci
+    import paper_2512_18345_amd as P
+    torch.cuda.set_device(0)
+    specs = [ci.get("serve_n15"), ci.get("serve_n16")]
+    ctxs = [P.Context.from_spec(s) for s in specs]
+    rng = ci.Rng(5)
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32).copy()).cuda()
+
+    keys = [dev(rng.evk(s)) for s in specs]
+    # one input pair per (N, L); a ring of output buffers per N
+    ins = {}
+    for c, s in enumerate(specs):
+        full1, full2 = rng.polys(2, s.q, s.N), rng.polys(2, s.q, s.N)
+        for L in range(2, s.L_max + 1):
+            ins[(c, L)] = (dev(full1[:, :L]), dev(full2[:, :L]))
+    RING = 256
+    outs = [[torch.empty(2 * s.L_max * s.N, dtype=torch.int32, device="cuda") for _ in range(RING)]
+            for s in specs]
+    max_slots = 32
+    srv = P.ckks_server_create([c.handle for c in ctxs], int(args.serve_budget_gib * (1 << 30)), max_slots)
+    counter = [0]
+
+    def make_request(r):
+        c = r.randrange(2)
+        L = r.randint(2, specs[c].L_max)
+        b = r.randint(1, 32)
+        op = P.JOB["KEYSWITCH"] if r.random() < 0.5 else P.JOB["HMULT"]
+        a1, a2 = ins[(c, L)]
+        jobs = []
+        for _ in range(b):
+            o = outs[c][counter[0] % RING]
+            counter[0] += 1
+            if op == P.JOB["KEYSWITCH"]:
+                jobs.append(dict(op=op, L=L, in0=a1[0], key=keys[c], out=o))
+            else:
+                jobs.append(dict(op=op, L=L, in0=a1, in1=a2, key=keys[c], out=o))
+        return c, jobs
+
+    def run(n_req, rate, seed):
+        r = random.Random(seed)
+        reqs = [make_request(r) for _ in range(n_req)]
+        first = P.ckks_server_stats(srv)["submitted"]
+        spans = []
+        t0 = time.perf_counter()
+        next_t = t0
+        for c, jobs in reqs:
+            if rate:
+                next_t += r.expovariate(rate)
+                while time.perf_counter() < next_t:
+                    pass
+            t_first = None
+            for j in jobs:
+                tk = P.ckks_server_submit(srv, c, j)
+                t_first = tk if t_first is None else t_first
+            spans.append((t_first, len(jobs)))
+        P.ckks_server_drain(srv)
+        wall = time.perf_counter() - t0
+        n_jobs = sum(n for _, n in spans)
+        sub, done = P.ckks_server_times(srv, first, n_jobs)
+        lat = []
+        for t_first, n in spans:
+            i = t_first - first
+            lat.append(max(done[i:i + n]) - sub[i])
+        lat = np.array(lat)
+        return {"requests": n_req, "jobs": n_jobs, "jobs_per_s": round(n_jobs / wall, 1),
+                "p50_us": round(float(np.percentile(lat, 50)), 1),
+                "p99_us": round(float(np.percentile(lat, 99)), 1)}
+
+    run(20, 0, 1)  # warm-up
+    sat = run(args.serve_requests, 0, 2)
+    mean_b = 16.5
+    loads = {}
+    for rho in (0.5, 0.8, 0.95):
+        loads[str(rho)] = run(args.serve_requests, rho * sat["jobs_per_s"] / mean_b, 3 + int(rho * 100))
+    st = P.ckks_server_stats(srv)
+    P.ckks_server_destroy(srv)
+    print(json.dumps({"serving": {"saturated": sat, "poisson": loads, "max_slots": max_slots,
+                                  "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"],
+                                  "batches": st["batches"]}}), flush=True)
 
 
 def cpu_baseline(spec, ct1, ct2, ctr, rot, rlk, rotk, budget_s):

@@ -76,6 +76,12 @@ def prime_chain(two_n: int, count: int, bits: int = 30) -> List[int]:
     return out
 
 
+# Shape of the bootstrapping-like operation trace: baby-step / giant-step
+# rotations of each linear-transform level and the length of the
+# multiplication chain between the two transforms.
+BOOT_TRACE = dict(levels=3, baby=list(range(1, 17)), giant=[16, 32, 48, 64], chain=12)
+
+
 @dataclasses.dataclass(frozen=True)
 class ChainSpec:
     """One parameter set: ring degree, Q chain, P chain, digit size."""
@@ -122,6 +128,8 @@ CONFIGS = {
     "n16_l36": dict(logN=16, L_max=36, k=12, dnum=3, seed=2),
     "batch_n16": dict(logN=16, L_max=36, k=12, dnum=3, seed=3),
     "boot_trace_n16": dict(logN=16, L_max=36, k=12, dnum=3, seed=4),
+    # the same trace shape on a small ring, for checking it against the oracle
+    "boot_trace_n12": dict(logN=12, L_max=36, k=12, dnum=3, seed=4),
     "serve_n15": dict(logN=15, L_max=36, k=12, dnum=3, seed=5, logN_max=16),
     "serve_n16": dict(logN=16, L_max=36, k=12, dnum=3, seed=5),
     # small chain for the toy CKKS semantic check: 6 + 2 primes, digit size 2

@@ -138,6 +138,20 @@ int ckks_tensor(const ckks_ctx *ctx, const uint32_t *ct1, const uint32_t *ct2, i
                 uint32_t *out, void *stream);
 
 /*
+ * Plaintext products summed, the inner sums of a baby-step giant-step linear
+ * transform (element-wise, Sec. II-B3): out[c][i] = sum_{b < nb} ct_b[c][i] *
+ * pt_b[i] mod q_i for c = 0, 1.  h_cts: nb device pointers to [2][L][N]
+ * ciphertexts; h_pts: nb device pointers to [L][N] evaluation-domain
+ * plaintexts; 1 <= nb <= 16.  out: [2][L][N], must not alias an input.
+ */
+int ckks_pmult_sum(const ckks_ctx *ctx, const uint32_t *const *h_cts, const uint32_t *const *h_pts,
+                   int nb, int L, uint32_t *out, void *stream);
+
+/* Ciphertext sum (element-wise): out = a + b over [2][L][N]; out may alias a or b. */
+int ckks_add(const ckks_ctx *ctx, const uint32_t *a, const uint32_t *b, int L, uint32_t *out,
+             void *stream);
+
+/*
  * ModUp, key-switching stage 1 (Fig. keysw, Sec. IV-A), for every digit j:
  * INTT of the digit's limbs, fast BConv (Sec. II-B2, III-C2) from D_j to the
  * other moduli of Q_L and P, NTT of the new limbs; the digit's own rows are
@@ -252,6 +266,49 @@ int ckks_batch_launch(ckks_batch *batch, void *stream);
 /* Device bytes the batch holds (tables + scratch). */
 size_t ckks_batch_device_bytes(const ckks_batch *batch);
 int ckks_batch_destroy(ckks_batch *batch);
+
+/*
+ * Serving loop: continuous batching of jobs under an HBM budget.
+ *
+ * A server owns a device arena of hbm_budget bytes (allocated at creation)
+ * from which every admitted job's scratch is taken, a few HIP streams, and
+ * one host worker thread.  ckks_server_submit queues a job for context
+ * ctxs[ctx_index] (contexts of different N may be mixed; all on one device)
+ * and returns a ticket at once.  The worker admits queued jobs in arrival
+ * order while fewer than max_slots jobs are on the device and the job's
+ * scratch fits in the arena, launches each admitted group as one batch (the
+ * job-table pipeline) on the next stream, and retires batches as their
+ * events complete, so requests arriving while others run are admitted as
+ * slots and memory free up and their work overlaps on the device.  A job's
+ * result is bitwise the same as in a single call.  Inputs, keys and outputs
+ * are caller-owned device buffers that must stay valid until the ticket is
+ * done.  A job whose scratch alone exceeds the budget is refused with
+ * CKKS_ENOMEM.  Latencies are host wall-clock from submit to the worker
+ * observing completion.
+ */
+typedef struct ckks_server ckks_server;
+
+typedef struct ckks_stats {
+    uint64_t submitted, completed, rejected, pending, in_flight, batches;
+    double p50_us, p99_us, mean_us, max_us;  /* submit -> completion, completed jobs */
+    double ks_per_s;                         /* completed key-switching jobs per second */
+    size_t budget_bytes, peak_bytes;         /* arena size, peak scratch in use */
+} ckks_stats;
+
+int ckks_server_create(const ckks_ctx *const *ctxs, int nctx, size_t hbm_budget, int max_slots,
+                       ckks_server **out);
+int ckks_server_submit(ckks_server *server, int ctx_index, const ckks_job *job, uint64_t *ticket);
+/* *done = 1 once the ticket's result is in its output buffer. */
+int ckks_server_poll(ckks_server *server, uint64_t ticket, int *done);
+/* Block until every submitted job has completed. */
+int ckks_server_drain(ckks_server *server);
+int ckks_server_stats(ckks_server *server, ckks_stats *stats);
+/* Submit / completion times (us since server creation; completion < 0 while
+ * pending) of tickets [first, first + n). */
+int ckks_server_times(ckks_server *server, uint64_t first, int n, double *h_submit_us,
+                      double *h_done_us);
+/* Finish all queued work, stop the worker, free the arena. */
+int ckks_server_destroy(ckks_server *server);
 
 /*
  * Kernel tracing.  Between ckks_trace_begin and ckks_trace_end, every launch

@@ -221,6 +221,23 @@ def scale(a, c: Sequence[int], primes):
     return (a.astype(U64) * _col([int(v) % int(q) for v, q in zip(c, primes)]) % _col(primes)).astype(U32)
 
 
+def pmult_sum(par: Params, cts, pts, L: int) -> np.ndarray:
+    """Sum of plaintext products (element-wise, Sec. II-B3): for c = 0, 1,
+    out[c] = sum_b ct_b[c] * pt_b over Q_L.  [2][L][N]."""
+    Q = par.q[:L]
+    out = np.zeros((2, L, par.N), dtype=U32)
+    for ct, pt in zip(cts, pts):
+        for c in range(2):
+            out[c] = add(out[c], mul(ct[c], pt[:L], Q), Q)
+    return out
+
+
+def ct_add(par: Params, a, b, L: int) -> np.ndarray:
+    """Ciphertext sum over Q_L: [2][L][N]."""
+    Q = par.q[:L]
+    return np.stack([add(a[c], b[c], Q) for c in range(2)])
+
+
 # ---------------------------------------------------------------------------
 # Automorphism (Sec. II-B3: a column permutation)
 # ---------------------------------------------------------------------------

@@ -19,7 +19,9 @@ __all__ = [
     "ckks_inner_product", "ckks_moddown", "ckks_keyswitch", "ckks_hmult",
     "ckks_hrot", "ckks_hrot_hoisted", "ckks_rescale", "ckks_trace_begin", "ckks_trace_end", "STAGE",
     "JOB", "ckks_job", "ckks_batch_create", "ckks_batch_launch", "ckks_batch_device_bytes",
-    "ckks_batch_destroy",
+    "ckks_batch_destroy", "ckks_stats", "ckks_server_create", "ckks_server_submit",
+    "ckks_server_poll", "ckks_server_drain", "ckks_server_stats", "ckks_server_times",
+    "ckks_server_destroy", "ckks_pmult_sum", "ckks_add",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -46,6 +48,20 @@ class ckks_job(ctypes.Structure):
                 ("key", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class ckks_stats(ctypes.Structure):
+    """Mirror of struct ckks_stats (include/ckks.h)."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+                ("in_flight", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("ks_per_s", ctypes.c_double), ("budget_bytes", ctypes.c_size_t),
+                ("peak_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -70,6 +86,15 @@ _SIGS = {
     "ckks_batch_create": [_vp, _vp, _i, _i, ctypes.POINTER(_vp)],
     "ckks_batch_launch": [_vp, _vp],
     "ckks_batch_destroy": [_vp],
+    "ckks_pmult_sum": [_vp, _vp, _vp, _i, _i, _vp, _vp],
+    "ckks_add": [_vp, _vp, _vp, _i, _vp, _vp],
+    "ckks_server_create": [_vp, _i, _sz, _i, ctypes.POINTER(_vp)],
+    "ckks_server_submit": [_vp, _i, _vp, ctypes.POINTER(ctypes.c_uint64)],
+    "ckks_server_poll": [_vp, ctypes.c_uint64, ctypes.POINTER(_i)],
+    "ckks_server_drain": [_vp],
+    "ckks_server_stats": [_vp, _vp],
+    "ckks_server_times": [_vp, ctypes.c_uint64, _i, _vp, _vp],
+    "ckks_server_destroy": [_vp],
     "ckks_trace_end": [_vp, _vp, ctypes.POINTER(_i)],
 }
 
@@ -233,6 +258,68 @@ def ckks_batch_device_bytes(batch) -> int:
 
 def ckks_batch_destroy(batch):
     _check(lib().ckks_batch_destroy(batch))
+
+
+def ckks_pmult_sum(ctx, cts, pts, L, out, stream=None):
+    n = len(cts)
+    a = (_vp * n)(*[_ptr(t) for t in cts])
+    b = (_vp * n)(*[_ptr(t) for t in pts])
+    _check(lib().ckks_pmult_sum(ctx, ctypes.cast(a, _vp), ctypes.cast(b, _vp), n, L, _ptr(out),
+                                _stream(stream)))
+
+
+def ckks_add(ctx, a, b, L, out, stream=None):
+    _check(lib().ckks_add(ctx, _ptr(a), _ptr(b), L, _ptr(out), _stream(stream)))
+
+
+def _job(j):
+    if isinstance(j, ckks_job):
+        return j
+    return ckks_job(int(j["op"]), int(j["L"]), int(j.get("rot", 0)), 0, _ptr(j["in0"]),
+                    _ptr(j.get("in1")), _ptr(j.get("key")), _ptr(j["out"]))
+
+
+def ckks_server_create(ctxs, hbm_budget, max_slots) -> int:
+    arr = (_vp * len(ctxs))(*ctxs)
+    h = _vp()
+    _check(lib().ckks_server_create(ctypes.cast(arr, _vp), len(ctxs), int(hbm_budget), int(max_slots),
+                                    ctypes.byref(h)))
+    return h.value
+
+
+def ckks_server_submit(server, ctx_index, job) -> int:
+    j = _job(job)
+    t = ctypes.c_uint64(0)
+    _check(lib().ckks_server_submit(server, int(ctx_index), ctypes.cast(ctypes.byref(j), _vp),
+                                    ctypes.byref(t)))
+    return t.value
+
+
+def ckks_server_poll(server, ticket) -> bool:
+    d = _i(0)
+    _check(lib().ckks_server_poll(server, int(ticket), ctypes.byref(d)))
+    return bool(d.value)
+
+
+def ckks_server_drain(server):
+    _check(lib().ckks_server_drain(server))
+
+
+def ckks_server_stats(server) -> dict:
+    st = ckks_stats()
+    _check(lib().ckks_server_stats(server, ctypes.cast(ctypes.byref(st), _vp)))
+    return st.as_dict()
+
+
+def ckks_server_times(server, first, n):
+    a = (ctypes.c_double * max(n, 1))()
+    b = (ctypes.c_double * max(n, 1))()
+    _check(lib().ckks_server_times(server, int(first), int(n), ctypes.cast(a, _vp), ctypes.cast(b, _vp)))
+    return [a[i] for i in range(n)], [b[i] for i in range(n)]
+
+
+def ckks_server_destroy(server):
+    _check(lib().ckks_server_destroy(server))
 
 
 def ckks_trace_begin(ctx, stage, capacity):

@@ -166,6 +166,11 @@ int run_one(const Ctx& c, int kind, int L, uint32_t gal, const uint32_t* a, cons
 
 }  // namespace
 
+namespace ckks {
+int api_fail(int code, const std::string& msg) { return fail(code, msg); }
+uint32_t api_galois(const Ctx& c, int rot) { return galois(c, rot); }
+}  // namespace ckks
+
 struct ckks_batch {
   const Ctx* c = nullptr;
   int n_ks = 0, n_rs = 0, Lmax_ks = 0, Lmax_rs = 0;
@@ -299,6 +304,28 @@ int ckks_tensor(const ckks_ctx* ctx, const uint32_t* ct1, const uint32_t* ct2, i
   if (!ct1 || !ct2 || !out) return fail(CKKS_EINVAL, "null data pointer");
   DeviceGuard g(ctx->c.device);
   CKKS_TRY(launch_tensor(ctx->c, ct1, ct2, L, out, (hipStream_t)stream), "tensor");
+  return CKKS_OK;
+}
+
+int ckks_pmult_sum(const ckks_ctx* ctx, const uint32_t* const* h_cts, const uint32_t* const* h_pts,
+                   int nb, int L, uint32_t* out, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!h_cts || !h_pts || !out || nb < 1 || nb > 16) return fail(CKKS_EINVAL, "bad pmult_sum arguments");
+  for (int b = 0; b < nb; ++b)
+    if (!h_cts[b] || !h_pts[b]) return fail(CKKS_EINVAL, "null ciphertext or plaintext pointer");
+  DeviceGuard g(ctx->c.device);
+  CKKS_TRY(launch_pmult_sum(ctx->c, h_cts, h_pts, nb, L, out, (hipStream_t)stream), "pmult_sum");
+  return CKKS_OK;
+}
+
+int ckks_add(const ckks_ctx* ctx, const uint32_t* a, const uint32_t* b, int L, uint32_t* out,
+             void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!a || !b || !out) return fail(CKKS_EINVAL, "null data pointer");
+  DeviceGuard g(ctx->c.device);
+  CKKS_TRY(launch_ct_add(ctx->c, a, b, L, out, (hipStream_t)stream), "add");
   return CKKS_OK;
 }
 

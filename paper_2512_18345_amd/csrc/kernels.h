@@ -33,4 +33,9 @@ hipError_t launch_broadcast_mod(const Ctx& c, int rows, const uint32_t* t, uint3
 hipError_t launch_sub_scale(const Ctx& c, int rows, const uint32_t* a, const uint32_t* v,
                             const uint2* qinv, uint32_t* out, hipStream_t st);
 
+hipError_t launch_pmult_sum(const Ctx& c, const uint32_t* const* cts, const uint32_t* const* pts, int nb,
+                            int L, uint32_t* out, hipStream_t st);
+hipError_t launch_ct_add(const Ctx& c, const uint32_t* a, const uint32_t* b, int L, uint32_t* out,
+                         hipStream_t st);
+
 }  // namespace ckks

@@ -20,13 +20,13 @@ namespace ckks {
 template <int LOGN1>
 __global__ __launch_bounds__(kWG) void k_ntt_cols(DevTab T, RowMap rm, const uint32_t* src,
                                                   uint32_t* dst, int skip_lo, int skip_hi) {
-  __shared__ __align__(16) uint32_t s[kLds];
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   const int r = blockIdx.y;
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
-  const int col0 = blockIdx.x * (kTile >> LOGN1);
+  const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
   load_cols<LOGN1>(s, src + r * N, col0);
   __syncthreads();
   col_stages<LOGN1, false>(s, T.col_tw(pi), q, q2);
@@ -99,8 +99,8 @@ template <int LOGN1>
 __global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const uint32_t* src,
                                                    uint32_t* dst, int skip_lo, int skip_hi,
                                                    const uint2* scale, int scale_off) {
-  __shared__ __align__(16) uint32_t s[kLds];
-  constexpr int C = kTile >> LOGN1;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
+  constexpr int C = ColGeom<LOGN1>::C;
   const int r = blockIdx.y;
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const ui
   __syncthreads();
   uint32_t* row = dst + r * N;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < ColGeom<LOGN1>::QUADS; ++k) {
     const int lin = (threadIdx.x + k * kWG) * 4;
     const int pos = lin / C, c = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
@@ -251,6 +251,38 @@ __global__ __launch_bounds__(kWG) void k_sub_scale(DevTab T, const uint32_t* a, 
   out[e] = csub(mul_shoup(a[e] + q - v[e], c.x, c.y, q), q);
 }
 
+// Plaintext products summed (the baby-step inner products of a BSGS linear
+// transform): out[c][i] = sum_b ct_b[c][i] * pt_b[i] mod q_i, b < nb <= 16.
+// Sixteen products of canonical residues stay below 2^64: one reduction.
+struct PtrList16 {
+  const uint32_t* p[16];
+};
+__global__ __launch_bounds__(kWG) void k_pmult_sum(DevTab T, PtrList16 cts, PtrList16 pts, int nb, int L,
+                                                   uint32_t* out) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const int i = blockIdx.y;
+  const ModC m = ldc(T.mod + i);
+  uint64_t a0 = 0, a1 = 0;
+  for (int b = 0; b < nb; ++b) {
+    const uint32_t pt = pts.p[b][(size_t)i * N + n];
+    a0 += (uint64_t)cts.p[b][(size_t)i * N + n] * pt;
+    a1 += (uint64_t)cts.p[b][((size_t)L + i) * N + n] * pt;
+  }
+  out[(size_t)i * N + n] = reduce64(a0, m.q, m.mu_hi, m.mu_lo);
+  out[((size_t)L + i) * N + n] = reduce64(a1, m.q, m.mu_hi, m.mu_lo);
+}
+
+// Ciphertext sum: out = a + b over [2][L][N].
+__global__ __launch_bounds__(kWG) void k_ct_add(DevTab T, const uint32_t* a, const uint32_t* b, int L,
+                                                uint32_t* out) {
+  const size_t N = (size_t)1 << T.logN;
+  const int r = blockIdx.y;  // 0 .. 2L-1
+  const uint32_t q = ldc(T.mod + (r % L)).q;
+  const size_t e = (size_t)r * N + (size_t)blockIdx.x * kWG + threadIdx.x;
+  out[e] = csub(a[e] + b[e], q);
+}
+
 // ============================================================================
 // Launchers
 // ============================================================================
@@ -270,7 +302,7 @@ hipError_t launch_ntt(const Ctx& c, const uint32_t* src, uint32_t* dst, int rows
   const int logN1 = c.logN - kBlockLog;
   const dim3 grid(c.N / kTile, rows);
 #define CALL(L1)                                                                              \
-  k_ntt_cols<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, src, dst, skip_lo, skip_hi);             \
+  k_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, rows), kWG, 0, st>>>(c.tab(), rm, src, dst, skip_lo, skip_hi); \
   k_ntt_blks<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, dst, dst, skip_lo, skip_hi);
   CKKS_DISPATCH_LOGN1(logN1, CALL)
 #undef CALL
@@ -285,7 +317,7 @@ hipError_t launch_intt(const Ctx& c, const uint32_t* src, uint32_t* dst, int row
   const dim3 grid(c.N / kTile, rows);
 #define CALL(L1)                                                                              \
   k_intt_blks<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, src, dst, skip_lo, skip_hi);            \
-  k_intt_cols<L1><<<grid, kWG, 0, st>>>(c.tab(), rm, dst, dst, skip_lo, skip_hi, scale, scale_off);
+  k_intt_cols<L1><<<dim3(ColGeom<L1>::TILES, rows), kWG, 0, st>>>(c.tab(), rm, dst, dst, skip_lo, skip_hi, scale, scale_off);
   CKKS_DISPATCH_LOGN1(logN1, CALL)
 #undef CALL
   return hipGetLastError();
@@ -352,6 +384,24 @@ hipError_t launch_sub_scale(const Ctx& c, int rows, const uint32_t* a, const uin
                             const uint2* qinv, uint32_t* out, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   k_sub_scale<<<dim3(c.N / kWG, rows), kWG, 0, st>>>(c.tab(), a, v, qinv, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pmult_sum(const Ctx& c, const uint32_t* const* cts, const uint32_t* const* pts, int nb,
+                            int L, uint32_t* out, hipStream_t st) {
+  if (nb < 1 || nb > 16) return hipErrorInvalidValue;
+  PtrList16 a{}, b{};
+  for (int i = 0; i < nb; ++i) {
+    a.p[i] = cts[i];
+    b.p[i] = pts[i];
+  }
+  k_pmult_sum<<<dim3(c.N / kWG, L), kWG, 0, st>>>(c.tab(), a, b, nb, L, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ct_add(const Ctx& c, const uint32_t* a, const uint32_t* b, int L, uint32_t* out,
+                         hipStream_t st) {
+  k_ct_add<<<dim3(c.N / kWG, 2 * L), kWG, 0, st>>>(c.tab(), a, b, L, out);
   return hipGetLastError();
 }
 

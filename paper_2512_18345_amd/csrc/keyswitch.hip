@@ -24,6 +24,8 @@
 // Sec. IV-A).  Rescale has its own four kernels (R1..R4).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "arith.h"
 #include "ctx.h"
 #include "keyswitch.h"
@@ -144,8 +146,8 @@ __global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA)
   const KsJob J = JA.get(blockIdx.z);
   const int r = blockIdx.y;
   if (J.kind == KS_HOIST || r >= J.L) return;
-  __shared__ __align__(16) uint32_t s[kLds];
-  constexpr int C = kTile >> LOGN1;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
+  constexpr int C = ColGeom<LOGN1>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + r).q, q2 = 2 * q;
   const uint2 sc = ldc(K.modup_scale + (size_t)J.L * K.T.L_max + r);
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA)
   col_stages<LOGN1, true>(s, K.T.col_itw(r), q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, c = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
@@ -208,10 +210,10 @@ __global__ __launch_bounds__(kWG) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) 
   if (j >= V.beta) return;
   const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
   if (r >= lo && r < hi) return;
-  __shared__ __align__(16) uint32_t s[kLds];
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
-  const int col0 = blockIdx.x * (kTile >> LOGN1);
+  const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
   uint32_t* row = V.z + (size_t)gr * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
@@ -335,6 +337,118 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
   }
 }
 
+// Variant of K5 for contexts with at most NB digits: every digit's tile is
+// staged and transformed in its own LDS slot first (all loads in flight at
+// once), then the inner product runs one 16-byte quad at a time, so the
+// 64-bit accumulators never hold more than four elements per component.
+template <int LOGN1, int NB>
+__global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const int logN = K.T.logN;
+  const size_t N = (size_t)1 << logN;
+  const KsView V = ks_view(J, K, N);
+  const int r = blockIdx.y;
+  if (r >= V.R || J.kind == KS_HOIST) return;
+  __shared__ __align__(16) uint32_t s[NB * kLds];
+  const int pi = ks_pidx(r, V.L, K.T.L_max);
+  const ModC m = ldc(K.T.mod + pi);
+  const uint32_t q = m.q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t base = blk0 * 256;
+  const size_t KR = (size_t)K.T.L_max + K.k;  // key rows
+
+  // stage every digit's tile: the transformed ModUp row, or the digit row itself
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j >= V.beta) break;
+    const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
+    uint32_t* slot = s + j * kLds;
+    if (r >= lo && r < hi) {
+      const uint32_t* drow = (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int e = blk_elem(kk);
+        lds_blk4_store(slot, e, *reinterpret_cast<const uint4*>(drow + e));
+      }
+    } else {
+      const uint32_t* zrow = V.z + ((size_t)j * V.R + r) * N + base;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int e = blk_elem(kk);
+        lds_blk4_store(slot, e, twist4(*reinterpret_cast<const uint4*>(zrow + e),
+                                       K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j >= V.beta) break;
+    const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
+    if (!(r >= lo && r < hi)) {
+      blk_stages<false>(s + j * kLds, K.T.blk_tw(pi), q, q2);
+      __syncthreads();
+    }
+  }
+
+  // inner product, one quad at a time (one reduction per output, Sec. III-C2)
+  uint4 res0[4], res1[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    uint64_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j >= V.beta) break;
+      const uint4 v = canon4(lds_blk4(s + j * kLds, e), q, q2);
+      const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pi) * N + base + e;
+      const uint4 e0 = *reinterpret_cast<const uint4*>(k0);
+      const uint4 e1 = *reinterpret_cast<const uint4*>(k0 + KR * N);
+      a0[0] += (uint64_t)v.x * e0.x;
+      a0[1] += (uint64_t)v.y * e0.y;
+      a0[2] += (uint64_t)v.z * e0.z;
+      a0[3] += (uint64_t)v.w * e0.w;
+      a1[0] += (uint64_t)v.x * e1.x;
+      a1[1] += (uint64_t)v.y * e1.y;
+      a1[2] += (uint64_t)v.z * e1.z;
+      a1[3] += (uint64_t)v.w * e1.w;
+    }
+    res0[kk] = make_uint4(reduce64(a0[0], q, m.mu_hi, m.mu_lo), reduce64(a0[1], q, m.mu_hi, m.mu_lo),
+                          reduce64(a0[2], q, m.mu_hi, m.mu_lo), reduce64(a0[3], q, m.mu_hi, m.mu_lo));
+    res1[kk] = make_uint4(reduce64(a1[0], q, m.mu_hi, m.mu_lo), reduce64(a1[1], q, m.mu_hi, m.mu_lo),
+                          reduce64(a1[2], q, m.mu_hi, m.mu_lo), reduce64(a1[3], q, m.mu_hi, m.mu_lo));
+  }
+  uint32_t* acc0 = V.acc + (size_t)r * N + base;
+  uint32_t* acc1 = V.acc + ((size_t)V.R + r) * N + base;
+  if (r < V.L) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int e = blk_elem(kk);
+      *reinterpret_cast<uint4*>(acc0 + e) = res0[kk];
+      *reinterpret_cast<uint4*>(acc1 + e) = res1[kk];
+    }
+    return;
+  }
+  // P rows: the INTT block pass of ModDown on both components (slots 0 and 1)
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    lds_blk4_store(s, blk_elem(kk), res0[kk]);
+    lds_blk4_store(s + kLds, blk_elem(kk), res1[kk]);
+  }
+  __syncthreads();
+  blk_stages<true>(s, K.T.blk_itw(pi), q, q2);
+  blk_stages<true>(s + kLds, K.T.blk_itw(pi), q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    const uint2* tb = K.T.blk_itwist(pi, blk0 + (e >> 8));
+    *reinterpret_cast<uint4*>(acc0 + e) = twist4(lds_blk4(s, e), tb, e & 255, q);
+    *reinterpret_cast<uint4*>(acc1 + e) = twist4(lds_blk4(s + kLds, e), tb, e & 255, q);
+  }
+}
+
 // ============================================================================
 // Stage 3: ModDown of both components
 // ============================================================================
@@ -346,8 +460,8 @@ __global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> J
   const size_t N = (size_t)1 << K.T.logN;
   const KsView V = ks_view(J, K, N);
   const int c = blockIdx.y / K.k, mm = blockIdx.y % K.k;
-  __shared__ __align__(16) uint32_t s[kLds];
-  constexpr int C = kTile >> LOGN1;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
+  constexpr int C = ColGeom<LOGN1>::C;
   const int pi = K.T.L_max + mm;
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
   const uint2 sc = ldc(K.moddown_scale + mm);
@@ -358,7 +472,7 @@ __global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> J
   __syncthreads();
   uint32_t* row = V.x + ((size_t)c * K.k + mm) * N;
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
@@ -401,9 +515,9 @@ __global__ __launch_bounds__(kWG) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA
   const int gr = blockIdx.y;
   if (gr >= 2 * V.L) return;
   const int i = gr % V.L;
-  __shared__ __align__(16) uint32_t s[kLds];
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
-  const int col0 = blockIdx.x * (kTile >> LOGN1);
+  const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
   uint32_t* row = V.w + (size_t)gr * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
@@ -512,8 +626,8 @@ template <int LOGN1>
 __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, pi = J.L - 1;
-  __shared__ __align__(16) uint32_t s[kLds];
-  constexpr int C = kTile >> LOGN1;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
+  constexpr int C = ColGeom<LOGN1>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const ModC m = ldc(K.T.mod + pi);
   const uint32_t q = m.q, q2 = 2 * q;
@@ -524,7 +638,7 @@ __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA)
   col_stages<LOGN1, true>(s, K.T.col_itw(pi), q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
@@ -544,15 +658,15 @@ __global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) 
   const int gr = blockIdx.y;
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
-  __shared__ __align__(16) uint32_t s[kLds];
-  constexpr int C = kTile >> LOGN1;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
+  constexpr int C = ColGeom<LOGN1>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const ModC m = ldc(K.T.mod + i);
   const uint32_t q = m.q, q2 = 2 * q;
   const int col0 = blockIdx.x * C;
   const uint32_t* t = J.ws + (size_t)c * N;
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(t + pos * 256 + col0 + cc);
@@ -618,7 +732,7 @@ size_t ks_hoist_ws_words(const Ctx& c, int L) {
 size_t rs_ws_words(const Ctx& c, int L) { return (2 + 2 * (size_t)L) * c.N; }
 
 namespace {
-constexpr int kRB = 4;  // BConv output rows per work-group
+constexpr int kRB = 12;  // BConv output rows per work-group (inputs re-read once per group)
 
 template <int A>
 hipError_t launch_k3(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int groups) {
@@ -671,29 +785,35 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     k1_intt_blks<L1><<<dim3(tiles, Lmax, njobs), kWG, 0, st>>>(K, jobs);
     c.trace_post(CKKS_STAGE_INTT_BLOCKS, st);
     c.trace_pre(CKKS_STAGE_INTT_COLS, st);
-    k2_intt_cols<L1><<<dim3(tiles, Lmax, njobs), kWG, 0, st>>>(K, jobs);
+    k2_intt_cols<L1><<<dim3(ColGeom<L1>::TILES, Lmax, njobs), kWG, 0, st>>>(K, jobs);
     c.trace_post(CKKS_STAGE_INTT_COLS, st);
     c.trace_pre(CKKS_STAGE_BCONV_UP, st);
     e = small_dispatch<K3, 1>(c.alpha, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
     c.trace_post(CKKS_STAGE_BCONV_UP, st);
     if (e != hipSuccess) return e;
     c.trace_pre(CKKS_STAGE_NTT_COLS_UP, st);
-    k4_ntt_cols<L1><<<dim3(tiles, bmax * Rmax, njobs), kWG, 0, st>>>(K, jobs);
+    k4_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), kWG, 0, st>>>(K, jobs);
     c.trace_post(CKKS_STAGE_NTT_COLS_UP, st);
     c.trace_pre(CKKS_STAGE_NTT_IP, st);
-    k5_ntt_blks_ip<L1, false><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
+    const dim3 g5(tiles, Rmax, njobs);
+    switch (std::max(c.beta_max(), 2)) {
+      case 2: k5s_ntt_blks_ip<L1, 2><<<g5, kWG, 0, st>>>(K, jobs); break;
+      case 3: k5s_ntt_blks_ip<L1, 3><<<g5, kWG, 0, st>>>(K, jobs); break;
+      case 4: k5s_ntt_blks_ip<L1, 4><<<g5, kWG, 0, st>>>(K, jobs); break;
+      default: k5_ntt_blks_ip<L1, false><<<g5, kWG, 0, st>>>(K, jobs); break;
+    }
     c.trace_post(CKKS_STAGE_NTT_IP, st);
   }
   if (with_hoist) k5_ntt_blks_ip<L1, true><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
   c.trace_pre(CKKS_STAGE_INTT_COLS_P, st);
-  k6_intt_cols_p<L1><<<dim3(tiles, 2 * c.k, njobs), kWG, 0, st>>>(K, jobs);
+  k6_intt_cols_p<L1><<<dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), kWG, 0, st>>>(K, jobs);
   c.trace_post(CKKS_STAGE_INTT_COLS_P, st);
   c.trace_pre(CKKS_STAGE_BCONV_DOWN, st);
   e = small_dispatch<K7, 1>(c.k, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
   c.trace_post(CKKS_STAGE_BCONV_DOWN, st);
   if (e != hipSuccess) return e;
   c.trace_pre(CKKS_STAGE_NTT_COLS_DOWN, st);
-  k8_ntt_cols_w<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
+  k8_ntt_cols_w<L1><<<dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
   c.trace_post(CKKS_STAGE_NTT_COLS_DOWN, st);
   c.trace_pre(CKKS_STAGE_NTT_COMBINE, st);
   k9_ntt_blks_combine<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
@@ -706,8 +826,8 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
                        int Lmax, hipStream_t st) {
   const int tiles = c.N / kTile;
   r1_intt_blks<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
-  r2_intt_cols<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
-  r3_ntt_cols<L1><<<dim3(tiles, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
+  r2_intt_cols<L1><<<dim3(ColGeom<L1>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
+  r3_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
   c.trace_pre(CKKS_STAGE_RESCALE_NTT, st);
   r4_ntt_blks_combine<L1><<<dim3(tiles, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
   c.trace_post(CKKS_STAGE_RESCALE_NTT, st);

@@ -16,17 +16,30 @@
 
 namespace ckks {
 
-constexpr int kLds = 4352;  // padded tile: 4096 + 256 words (both layouts)
+constexpr int kLds = 4352;  // padded block-pass tile: 16 x (256 + 16) words
+
+// Column-pass tile for N1 = 2^LOGN1 rows: C adjacent columns, at least 32 so
+// that every row segment is a whole 128-byte line (narrower tiles fetch each
+// line twice).
+template <int LOGN1>
+struct ColGeom {
+  static constexpr int N1 = 1 << LOGN1;
+  static constexpr int C = (kTile >> LOGN1) < 32 ? 32 : (kTile >> LOGN1);
+  static constexpr int ELEMS = C * N1;             // 4096 or 8192
+  static constexpr int QUADS = ELEMS / (4 * kWG);  // 16-byte quads per thread in load/store
+  static constexpr int LDS = ELEMS + N1;           // with the 16-word pad per 16 rows
+  static constexpr int TILES = 256 / C;            // column tiles per limb
+};
 
 __device__ __forceinline__ int lidx_col(int pos, int c, int C) { return pos * C + c + ((pos >> 4) << 4); }
 __device__ __forceinline__ int lidx_blk(int line, int pos) { return line * 272 + pos + (pos >> 4); }
 
 // ----- column-pass phases (stages on pos bits [blo, blo + LOGR)) -----------
-template <int LOGR, bool INV>
+template <int LOGR, bool INV, int ELEMS>
 __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo,
                                           const uint2* __restrict__ tw, uint32_t q, uint32_t q2) {
   constexpr int R = 1 << LOGR;
-  constexpr int GPT = 16 / R;
+  constexpr int GPT = ELEMS / R / kWG;
 #pragma unroll
   for (int gg = 0; gg < GPT; ++gg) {
     const int g = threadIdx.x + gg * kWG;
@@ -130,19 +143,19 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const uint2* __r
 // All column stages of one tile, forward (high bits first) or inverse (low bits first).
 template <int LOGN1, bool INV>
 __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
-  constexpr int C = kTile >> LOGN1;
+  using G = ColGeom<LOGN1>;
   constexpr int REM = LOGN1 - 4;  // 0..4
   if (!INV) {
-    col_phase<4, false>(s, LOGN1, C, REM, tw, q, q2);
+    col_phase<4, false, G::ELEMS>(s, LOGN1, G::C, REM, tw, q, q2);
     if constexpr (REM > 0) {
       __syncthreads();
-      col_phase<(REM > 0 ? REM : 1), false>(s, LOGN1, C, 0, tw, q, q2);
+      col_phase<(REM > 0 ? REM : 1), false, G::ELEMS>(s, LOGN1, G::C, 0, tw, q, q2);
     }
   } else {
-    col_phase<4, true>(s, LOGN1, C, 0, tw, q, q2);
+    col_phase<4, true, G::ELEMS>(s, LOGN1, G::C, 0, tw, q, q2);
     if constexpr (REM > 0) {
       __syncthreads();
-      col_phase<(REM > 0 ? REM : 1), true>(s, LOGN1, C, 4, tw, q, q2);
+      col_phase<(REM > 0 ? REM : 1), true, G::ELEMS>(s, LOGN1, G::C, 4, tw, q, q2);
     }
   }
 }
@@ -175,27 +188,36 @@ __device__ __forceinline__ uint4 twist4(uint4 v, const uint2* __restrict__ tb, i
 }
 
 // ----- tile load / store helpers --------------------------------------------
+// Thread t's k-th quad of a column tile: tile-linear word 4 (t + 256 k) = (pos, c).
+template <int LOGN1>
+__device__ __forceinline__ void col_quad(int k, int& pos, int& c) {
+  using G = ColGeom<LOGN1>;
+  const int lin = (threadIdx.x + k * kWG) * 4;
+  pos = lin / G::C;
+  c = lin & (G::C - 1);
+}
+
 template <int LOGN1>
 __device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restrict__ row, int col0) {
-  constexpr int C = kTile >> LOGN1;
+  using G = ColGeom<LOGN1>;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int lin = (threadIdx.x + k * kWG) * 4;
-    const int pos = lin / C, c = lin & (C - 1);
+  for (int k = 0; k < G::QUADS; ++k) {
+    int pos, c;
+    col_quad<LOGN1>(k, pos, c);
     const uint4 v = *reinterpret_cast<const uint4*>(row + pos * 256 + col0 + c);
-    *reinterpret_cast<uint4*>(s + lidx_col(pos, c, C)) = v;
+    *reinterpret_cast<uint4*>(s + lidx_col(pos, c, G::C)) = v;
   }
 }
 
 template <int LOGN1>
 __device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restrict__ row, int col0) {
-  constexpr int C = kTile >> LOGN1;
+  using G = ColGeom<LOGN1>;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int lin = (threadIdx.x + k * kWG) * 4;
-    const int pos = lin / C, c = lin & (C - 1);
+  for (int k = 0; k < G::QUADS; ++k) {
+    int pos, c;
+    col_quad<LOGN1>(k, pos, c);
     *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) =
-        *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
+        *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, G::C));
   }
 }
 

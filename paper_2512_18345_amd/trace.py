@@ -1,0 +1,62 @@
+"""Bootstrapping-shaped operation trace over the C-ABI (a workload driver).
+
+Shape (the linear transforms of bootstrapping around a multiplication
+chain, on uniform residues):  three linear-transform levels, each = one
+hoisted group of 16 baby-step rotations sharing one ModUp, four inner sums
+of 16 plaintext products, four giant-step rotations, their sum and a
+rescale; a chain of 12 squarings (HMult) with rescales; three more
+linear-transform levels.  132 key-switches; L drops 36 -> 33 -> 21 -> 18 at
+the default parameters.  Every step is a library call on the given stream.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (ckks_add, ckks_hmult, ckks_hrot, ckks_hrot_hoisted, ckks_pmult_sum,
+               ckks_rescale)
+
+
+def key_switches(shape) -> int:
+    per_level = len(shape["baby"]) + len(shape["giant"])
+    return 2 * shape["levels"] * per_level + shape["chain"]
+
+
+def run(ctx, ct, L, shape, rotkeys, rlk, pts, stream=None):
+    """ct: [2][L][N] device tensor; rotkeys: {rotation: key}; pts: list of
+    plaintexts [L_max][N] (the first L rows are used).  Returns (ct, L)."""
+    N, h = ctx.N, ctx.handle
+    ws = {op: ctx.workspace(op, L) for op in ("HROT", "HMULT", "RESCALE", "HROT_HOISTED")}
+
+    def empty(*shape_):
+        return torch.empty(shape_, dtype=torch.int32, device=ct.device)
+
+    def lin_transform(ct, L):
+        baby, giant = shape["baby"], shape["giant"]
+        rotated = [empty(2, L, N) for _ in baby]
+        ckks_hrot_hoisted(h, ct, L, baby, [rotkeys[r] for r in baby], rotated, ws["HROT_HOISTED"], stream)
+        acc = None
+        for g, rg in enumerate(giant):
+            group = pts[g * len(baby):(g + 1) * len(baby)]
+            inner = empty(2, L, N)
+            ckks_pmult_sum(h, rotated, [p[:L] for p in group], L, inner, stream)
+            out = empty(2, L, N)
+            ckks_hrot(h, inner, L, rg, rotkeys[rg], out, ws["HROT"], stream)
+            if acc is None:
+                acc = out
+            else:
+                ckks_add(h, acc, out, L, acc, stream)
+        res = empty(2, L - 1, N)
+        ckks_rescale(h, acc, L, res, ws["RESCALE"], stream)
+        return res, L - 1
+
+    for _ in range(shape["levels"]):
+        ct, L = lin_transform(ct, L)
+    for _ in range(shape["chain"]):
+        m = empty(2, L, N)
+        ckks_hmult(h, ct, ct, L, rlk, m, ws["HMULT"], stream)
+        ct = empty(2, L - 1, N)
+        ckks_rescale(h, m, L, ct, ws["RESCALE"], stream)
+        L -= 1
+    for _ in range(shape["levels"]):
+        ct, L = lin_transform(ct, L)
+    return ct, L

@@ -51,3 +51,11 @@ def test_invalid_arguments_fail_without_touching_a_device():
     assert P.ckks_workspace_bytes(None, 3, 1) == 0
     with pytest.raises(P.CkksError):
         P.ckks_ntt(None, 0, 1, False, 0)
+
+
+def test_server_and_batch_argument_errors_without_a_device():
+    with pytest.raises(P.CkksError) as e:
+        P.ckks_server_create([], 1 << 20, 4)
+    assert e.value.code == -1
+    with pytest.raises(P.CkksError):
+        P.ckks_batch_create(None, [])

@@ -169,3 +169,21 @@ def test_toy_hoisted_rotations(toy):
             v = int(crt(rows, [int(x) for x in diff[:, n]])[0])
             v = v - Mod if v > Mod // 2 else v
             assert v % Dj == 0 and abs(v // Dj) <= len(dig)
+
+
+def test_pmult_sum_and_add_by_brute_force():
+    par = _small_par(logN=4)
+    L = 3
+    Q = par.q[:L]
+    cts = [np.stack([_rand(par, Q, 10 + 2 * b), _rand(par, Q, 11 + 2 * b)]) for b in range(5)]
+    pts = [_rand(par, par.q, 40 + b) for b in range(5)]
+    got = O.pmult_sum(par, cts, pts, L)
+    for c in range(2):
+        for i, q in enumerate(Q):
+            for n in range(par.N):
+                want = sum(int(cts[b][c, i, n]) * int(pts[b][i, n]) for b in range(5)) % q
+                assert int(got[c, i, n]) == want
+    s = O.ct_add(par, cts[0], cts[1], L)
+    for c in range(2):
+        for i, q in enumerate(Q):
+            assert [int(v) for v in s[c, i]] == [(int(x) + int(y)) % q for x, y in zip(cts[0][c, i], cts[1][c, i])]
