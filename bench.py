@@ -26,6 +26,40 @@ sys.path.insert(0, ROOT)
 LIMB_BYTES = 4  # uint32 residues
 
 
+# Sources whose change invalidates a stored PMC traffic figure of the
+# key-switching kernels.
+KERNEL_SOURCES = ["paper_2512_18345_amd/csrc/" + f for f in
+                  ("keyswitch.hip", "keyswitch.h", "ntt_tile.h", "arith.h", "ctx.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k5s_ntt_blks_ip_q_rows_n16_l36_traffic.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE passes scaled by the copy
+    calibration), or None when the summary is missing or the kernel sources
+    changed after the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                key, _, v = line.partition(":")
+                vals[key.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash() or "bytes_per_launch" not in vals:
+        return None
+    return int(vals["bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,6 +76,8 @@ def parse():
                     help="only run the serving-loop benchmark (Poisson arrivals, p50/p99)")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the key-switching kernel sources (stored with PMC traffic)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling HBM counters)")
     return ap.parse_args()
@@ -63,6 +99,9 @@ def calibrate_copy(mib: int):
 
 def main():
     args = parse()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
@@ -115,9 +154,10 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # Dominant kernel: NTT block pass fused with the key inner product (stage 2
-    # of key-switching), timed by events around each of its launches on the
-    # stream it runs on, inside the timed region.
+    # Dominant kernel: NTT block pass fused with the key inner product over the
+    # L ciphertext-modulus rows (stage 2 of key-switching; it runs on the
+    # context's side stream, beside the P-row ModDown chain), timed by events
+    # around each of its launches on that stream, inside the timed region.
     ip_launches = 2 * args.steps
     P.ckks_trace_begin(h, P.STAGE["NTT_IP"], ip_launches)
     t0 = time.perf_counter()
@@ -145,19 +185,19 @@ def main():
     beta = ctx.beta(L)
     R = L + k
     limb = N * LIMB_BYTES
-    # per launch: the beta*R ModUp rows in, the 2*beta*R key rows in, the 2*R
-    # accumulator rows out
-    ip_bytes = (3 * beta + 2) * R * limb
+    # per launch (the L ciphertext-modulus rows): beta*L ModUp rows in,
+    # 2*beta*L key rows in, 2*L accumulator rows out
+    ip_bytes = (3 * beta + 2) * L * limb
     ip_us = 1e3 * float(np.mean(ip_ms))
     achieved = ip_bytes / (ip_us * 1e-6) / 1e9
     roofline = {
-        "kernel": "k5_ntt_blks_ip",
+        "kernel": "k5s_ntt_blks_ip (Q rows)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": 8000.0,
         "unit": "GB/s",
         "frac": round(achieved / 8000.0, 4),
-        "traffic": None,
+        "traffic": stored_traffic(),
         "avg_us": round(ip_us, 2),
         "launches": len(ip_ms),
         "bytes_per_launch": ip_bytes,
@@ -171,6 +211,13 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(spec, ct1, ct2, ctr, rot, rlk, rotk, args.cpu_seconds)
 
+    # Whole step against the HBM roofline with per-op algorithmic bytes
+    # (inputs + evk rows + outputs; intermediates on chip)
+    step_bytes = (_op_limbs("HMULT", L, k, beta) + _op_limbs("RESCALE", L, k, beta)
+                  + _op_limbs("HROT", L, k, beta)) * limb
+    path = {"bytes_per_step": step_bytes,
+            "GBps": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+            "frac": round(step_bytes / (ms_per_step * 1e-3) / 8e12, 4)}
     rec = {
         "metric": "key-switches/sec at N=2^16 (single-op HMult + rescale + HRot per step)",
         "value": round(value, 2),
@@ -189,6 +236,7 @@ def main():
         "hmult_latency_us": {"p50": round(float(np.percentile(lat, 50)), 2),
                              "p99": round(float(np.percentile(lat, 99)), 2),
                              "reps": int(len(lat))},
+        "path": path,
         "batched": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -197,13 +245,23 @@ def main():
     ctx.close()
 
 
+def _op_limbs(op, L, k, beta):
+    """Algorithmic HBM limbs of one job: inputs + evk rows at level L + output."""
+    if op == "RESCALE":
+        return 2 * L + 2 * (L - 1)
+    key = 2 * beta * (L + k)
+    return {"KEYSWITCH": L, "HMULT": 4 * L, "HROT": 2 * L}[op] + key + 2 * L
+
+
 def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
     """Batched key-switches/s on the same GPU: (a) 8 HMults at L=36, one
     batch (one captured graph) vs 8 single calls; (b) the 64-job mixed-level
     batch (levels uniform in 4..36; HMult 0.4, HRot 0.4 over 8 rotation keys,
-    rescale 0.2) as one captured graph."""
+    rescale 0.2) as one captured graph.  Each batch is timed with the default
+    plan and again after ckks_batch_tune picked its plan."""
     import torch
-    N, L = spec.N, spec.L_max
+    N, L, k = spec.N, spec.L_max, spec.k
+    limb = N * LIMB_BYTES
     stream = torch.cuda.current_stream()
 
     def timed(fn, n_ks):
@@ -215,13 +273,19 @@ def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
         torch.cuda.synchronize()
         return n_ks * reps / (time.perf_counter() - t0)
 
+    def default_and_tuned(b, n_ks):
+        default = timed(lambda: P.ckks_batch_launch(b, stream), n_ks)
+        plan, _ = P.ckks_batch_tune(b, 2, stream)
+        tuned = timed(lambda: P.ckks_batch_launch(b, stream), n_ks)
+        return default, tuned, plan
+
     # (a) same work, batched vs single-op
     outs = [torch.empty((2, L, N), dtype=torch.int32, device="cuda") for _ in range(8)]
     ws = ctx.workspace("HMULT", L)
     single = timed(lambda: [P.ckks_hmult(ctx.handle, d_ct1, d_ct2, L, d_rlk, o, ws, stream) for o in outs], 8)
     b8 = P.ckks_batch_create(ctx.handle, [dict(op=P.JOB["HMULT"], L=L, in0=d_ct1, in1=d_ct2, key=d_rlk,
                                                out=o) for o in outs], use_graph=True)
-    batched8 = timed(lambda: P.ckks_batch_launch(b8, stream), 8)
+    batched8, tuned8, plan8 = default_and_tuned(b8, 8)
     P.ckks_batch_destroy(b8)
     del outs, ws
 
@@ -229,34 +293,51 @@ def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
     rng = ci.Rng(3)
     keys = [dev(rng.evk(spec)) for _ in range(9)]  # 8 rotation keys + the relinearisation key
     jobs, n_ks, keep = [], 0, []
+    per_op, key_level = 0, {}
     for _ in range(64):
         Lj = int(rng.integers(4, 37))
         u = float(rng.integers(0, 10)) / 10.0
         a = dev(rng.polys(2, spec.q[:Lj], N))
         keep.append(a)
+        bj = ctx.beta(Lj)
         if u < 0.4:
             b = dev(rng.polys(2, spec.q[:Lj], N))
             keep.append(b)
             o = torch.empty((2, Lj, N), dtype=torch.int32, device="cuda")
             jobs.append(dict(op=P.JOB["HMULT"], L=Lj, in0=a, in1=b, key=keys[8], out=o))
             n_ks += 1
+            per_op += _op_limbs("HMULT", Lj, k, bj)
+            key_level[8] = max(key_level.get(8, 0), Lj)
         elif u < 0.8:
             o = torch.empty((2, Lj, N), dtype=torch.int32, device="cuda")
             r = int(rng.integers(0, 8))
             jobs.append(dict(op=P.JOB["HROT"], L=Lj, rot=1 + r, in0=a, key=keys[r], out=o))
             n_ks += 1
+            per_op += _op_limbs("HROT", Lj, k, bj)
+            key_level[r] = max(key_level.get(r, 0), Lj)
         else:
             o = torch.empty((2, Lj - 1, N), dtype=torch.int32, device="cuda")
             jobs.append(dict(op=P.JOB["RESCALE"], L=Lj, in0=a, out=o))
+            per_op += _op_limbs("RESCALE", Lj, k, bj)
         keep.append(o)
+    # workload-compulsory: every distinct key read once (rows of its largest level)
+    keys_once = sum(2 * ctx.beta(Lk) * (Lk + k) for Lk in key_level.values())
+    key_per_op = sum(2 * ctx.beta(j["L"]) * (j["L"] + k) for j in jobs if j["op"] != P.JOB["RESCALE"])
+    compulsory = per_op - key_per_op + keys_once
     b64 = P.ckks_batch_create(ctx.handle, jobs, use_graph=True)
-    mixed = timed(lambda: P.ckks_batch_launch(b64, stream), n_ks)
+    mixed, mixed_tuned, plan64 = default_and_tuned(b64, n_ks)
     P.ckks_batch_destroy(b64)
+    launch_s = n_ks / mixed_tuned
     return {"hmult_L36_x8": {"single_op_ks_per_s": round(single, 1),
                              "batched_graph_ks_per_s": round(batched8, 1),
-                             "speedup": round(batched8 / single, 3)},
-            "mixed_64_jobs_L4_36": {"ks_per_s": round(mixed, 1), "key_switches": n_ks,
-                                    "jobs": 64, "graph": True}}
+                             "tuned_ks_per_s": round(tuned8, 1), "tuned_plan": plan8,
+                             "speedup": round(max(batched8, tuned8) / single, 3)},
+            "mixed_64_jobs_L4_36": {"ks_per_s": round(mixed, 1), "tuned_ks_per_s": round(mixed_tuned, 1),
+                                    "tuned_plan": plan64, "key_switches": n_ks, "jobs": 64, "graph": True,
+                                    "per_op_bytes": per_op * limb, "compulsory_bytes": compulsory * limb,
+                                    "per_op_GBps": round(per_op * limb / launch_s / 1e9, 1),
+                                    "compulsory_GBps": round(compulsory * limb / launch_s / 1e9, 1),
+                                    "compulsory_frac": round(compulsory * limb / launch_s / 8e12, 4)}}
 
 
 def boot_trace_bench(args):

@@ -76,12 +76,14 @@ enum {
     CKKS_STAGE_INTT_COLS = 2,       /* K2: INTT column pass + BConv pre-multiply */
     CKKS_STAGE_BCONV_UP = 3,        /* K3: ModUp base conversion, all digits */
     CKKS_STAGE_NTT_COLS_UP = 4,     /* K4: NTT column pass of the ModUp rows */
-    CKKS_STAGE_NTT_IP = 5,          /* K5: NTT block pass + key inner product (+ P-row INTT pass) */
+    CKKS_STAGE_NTT_IP = 5,          /* K5: NTT block pass + key inner product (+ P-row INTT pass);
+                                       the Q rows only when the inner product is split */
     CKKS_STAGE_INTT_COLS_P = 6,     /* K6: INTT column pass of the P rows */
     CKKS_STAGE_BCONV_DOWN = 7,      /* K7: ModDown base conversion */
     CKKS_STAGE_NTT_COLS_DOWN = 8,   /* K8: NTT column pass of the ModDown rows */
     CKKS_STAGE_NTT_COMBINE = 9,     /* K9: NTT block pass + (acc - w) P^-1 + epilogue */
-    CKKS_STAGE_RESCALE_NTT = 10     /* R4: rescale NTT block pass + combine */
+    CKKS_STAGE_RESCALE_NTT = 10,    /* R4: rescale NTT block pass + combine */
+    CKKS_STAGE_NTT_IP_P = 11        /* K5 on the P rows when the inner product is split */
 };
 
 typedef struct ckks_ctx ckks_ctx;
@@ -226,10 +228,11 @@ int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, 
 /*
  * Batches (Sec. IV-A batching; Sec. IV-C one submission per static graph).
  * A batch is a fixed list of independent jobs, each at its own level, run
- * together: every pipeline kernel covers all jobs of the batch at once
- * (nine kernels for all key-switching jobs, four for all rescale jobs), and
- * with use_graph != 0 the whole launch sequence is captured once into a
- * hipGraph at creation, so ckks_batch_launch is a single graph submission.
+ * together: every pipeline kernel covers all jobs of a launch group at once
+ * (nine kernels for the key-switching jobs of a group, four for all rescale
+ * jobs; groups as in ckks_batch_plan below), and with use_graph != 0 the
+ * whole launch sequence is captured once into a hipGraph at creation, so
+ * ckks_batch_launch is a single graph submission.
  * Each job's result is bitwise the result of the corresponding single call.
  */
 enum {
@@ -263,6 +266,42 @@ int ckks_batch_create(const ckks_ctx *ctx, const ckks_job *h_jobs, int n, int us
                       ckks_batch **out);
 /* Enqueue the whole batch on `stream` (asynchronous). */
 int ckks_batch_launch(ckks_batch *batch, void *stream);
+
+/*
+ * Launch plan of a batch (Sec. IV-A: the batch size B trades parallelism
+ * against the working set that stays in the caches).  The key-switching jobs
+ * are held in non-increasing level order (jobs of one level that share a key
+ * adjacent); consecutive groups of jobs_per_launch of them (0 = all) each
+ * run the pipeline once, group g on branch g mod streams; branches are
+ * streams forked from and joined back to the launch stream, so groups
+ * overlap on the device; split = 1 runs the Q-row inner product of each
+ * group on a side stream beside the P-row ModDown chain (Sec. IV-B).
+ * Rescale jobs run on the last branch.  Every plan gives bitwise the same
+ * results.  Default {0, 1, 1}.
+ */
+typedef struct ckks_batch_plan {
+    int jobs_per_launch;  /* >= 0 */
+    int streams;          /* 1..4 */
+    int split;            /* 0 or 1 */
+    int reserved;
+} ckks_batch_plan;
+
+int ckks_batch_get_plan(const ckks_batch *batch, ckks_batch_plan *plan);
+/* Replace the plan (re-captures the graph of a graph batch).  Synchronous
+ * for graph batches; must not overlap a launch of the same batch. */
+int ckks_batch_set_plan(ckks_batch *batch, const ckks_batch_plan *plan);
+/*
+ * Autotuner: times candidate plans (jobs_per_launch in {all, 32, 16, 8, 4, 2}
+ * below the job count, streams 1..4 up to the number of groups, split 0/1),
+ * each as one warm-up launch then `reps` launches between two events on
+ * `stream`, and keeps the fastest (graph batches are re-captured and timed as
+ * graph launches).  Runs the batch up to 48 x (reps + 1) times and
+ * synchronises `stream`: outputs are written, inputs only read.  best /
+ * best_us (either may be NULL) receive the chosen plan and its time per
+ * launch in microseconds.  On error the previous plan is kept.
+ */
+int ckks_batch_tune(ckks_batch *batch, int reps, void *stream, ckks_batch_plan *best,
+                    float *best_us);
 /* Device bytes the batch holds (tables + scratch). */
 size_t ckks_batch_device_bytes(const ckks_batch *batch);
 int ckks_batch_destroy(ckks_batch *batch);

@@ -19,7 +19,8 @@ __all__ = [
     "ckks_inner_product", "ckks_moddown", "ckks_keyswitch", "ckks_hmult",
     "ckks_hrot", "ckks_hrot_hoisted", "ckks_rescale", "ckks_trace_begin", "ckks_trace_end", "STAGE",
     "JOB", "ckks_job", "ckks_batch_create", "ckks_batch_launch", "ckks_batch_device_bytes",
-    "ckks_batch_destroy", "ckks_stats", "ckks_server_create", "ckks_server_submit",
+    "ckks_batch_destroy", "ckks_batch_plan", "ckks_batch_get_plan", "ckks_batch_set_plan",
+    "ckks_batch_tune", "ckks_stats", "ckks_server_create", "ckks_server_submit",
     "ckks_server_poll", "ckks_server_drain", "ckks_server_stats", "ckks_server_times",
     "ckks_server_destroy", "ckks_pmult_sum", "ckks_add",
 ]
@@ -29,7 +30,7 @@ LIB_PATH = os.path.join(HERE, "libckks.so")
 
 OP = dict(NTT=0, MODUP=1, MODDOWN=2, KEYSWITCH=3, HMULT=4, HROT=5, RESCALE=6, HROT_HOISTED=7)
 STAGE = dict(INTT_BLOCKS=1, INTT_COLS=2, BCONV_UP=3, NTT_COLS_UP=4, NTT_IP=5, INTT_COLS_P=6,
-             BCONV_DOWN=7, NTT_COLS_DOWN=8, NTT_COMBINE=9, RESCALE_NTT=10)
+             BCONV_DOWN=7, NTT_COLS_DOWN=8, NTT_COMBINE=9, RESCALE_NTT=10, NTT_IP_P=11)
 
 
 class CkksError(RuntimeError):
@@ -46,6 +47,15 @@ class ckks_job(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("L", ctypes.c_int), ("rot", ctypes.c_int),
                 ("reserved", ctypes.c_int), ("in0", ctypes.c_void_p), ("in1", ctypes.c_void_p),
                 ("key", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class ckks_batch_plan(ctypes.Structure):
+    """Mirror of struct ckks_batch_plan (include/ckks.h)."""
+    _fields_ = [("jobs_per_launch", ctypes.c_int), ("streams", ctypes.c_int),
+                ("split", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        return dict(jobs_per_launch=self.jobs_per_launch, streams=self.streams, split=self.split)
 
 
 class ckks_stats(ctypes.Structure):
@@ -86,6 +96,9 @@ _SIGS = {
     "ckks_batch_create": [_vp, _vp, _i, _i, ctypes.POINTER(_vp)],
     "ckks_batch_launch": [_vp, _vp],
     "ckks_batch_destroy": [_vp],
+    "ckks_batch_get_plan": [_vp, _vp],
+    "ckks_batch_set_plan": [_vp, _vp],
+    "ckks_batch_tune": [_vp, _i, _vp, _vp, _vp],
     "ckks_pmult_sum": [_vp, _vp, _vp, _i, _i, _vp, _vp],
     "ckks_add": [_vp, _vp, _vp, _i, _vp, _vp],
     "ckks_server_create": [_vp, _i, _sz, _i, ctypes.POINTER(_vp)],
@@ -258,6 +271,26 @@ def ckks_batch_device_bytes(batch) -> int:
 
 def ckks_batch_destroy(batch):
     _check(lib().ckks_batch_destroy(batch))
+
+
+def ckks_batch_get_plan(batch) -> dict:
+    p = ckks_batch_plan()
+    _check(lib().ckks_batch_get_plan(batch, ctypes.cast(ctypes.byref(p), _vp)))
+    return p.as_dict()
+
+
+def ckks_batch_set_plan(batch, jobs_per_launch=0, streams=1, split=1):
+    p = ckks_batch_plan(int(jobs_per_launch), int(streams), int(split), 0)
+    _check(lib().ckks_batch_set_plan(batch, ctypes.cast(ctypes.byref(p), _vp)))
+
+
+def ckks_batch_tune(batch, reps=3, stream=None):
+    """Autotune the batch's plan; returns (plan dict, microseconds per launch)."""
+    p = ckks_batch_plan()
+    us = ctypes.c_float()
+    _check(lib().ckks_batch_tune(batch, int(reps), _stream(stream),
+                                 ctypes.cast(ctypes.byref(p), _vp), ctypes.cast(ctypes.byref(us), _vp)))
+    return p.as_dict(), float(us.value)
 
 
 def ckks_pmult_sum(ctx, cts, pts, L, out, stream=None):

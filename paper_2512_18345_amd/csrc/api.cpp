@@ -160,7 +160,9 @@ int run_one(const Ctx& c, int kind, int L, uint32_t gal, const uint32_t* a, cons
   JobArg<KsJob> ja{};
   ja.table = nullptr;
   ja.inl[0] = KsJob{kind, L, gal, 0, a, b, key, out, (uint32_t*)ws};
-  CKKS_TRY(ks_launch(c, ja, 1, L, true, false, st), "key-switching pipeline");
+  std::lock_guard<std::mutex> lk(c.side_mu);
+  CKKS_TRY(ks_launch(c, ja, 1, L, true, false, st, KsSplit{c.side, c.fork_ev, c.join_ev}),
+           "key-switching pipeline");
   return CKKS_OK;
 }
 
@@ -171,38 +173,109 @@ int api_fail(int code, const std::string& msg) { return fail(code, msg); }
 uint32_t api_galois(const Ctx& c, int rot) { return galois(c, rot); }
 }  // namespace ckks
 
+constexpr int kMaxBranches = 4;
+
 struct ckks_batch {
   const Ctx* c = nullptr;
-  int n_ks = 0, n_rs = 0, Lmax_ks = 0, Lmax_rs = 0;
+  int n_ks = 0, n_rs = 0, Lmax_rs = 0;
+  std::vector<int> L_ks;  // levels of the key-switching jobs in table order (non-increasing)
   KsJob* d_ks = nullptr;
   RsJob* d_rs = nullptr;
   void* d_ws = nullptr;
   size_t bytes = 0;
+  bool use_graph = false;
+  ckks_batch_plan plan{0, 1, 1, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;
+  // branch 0 is the launch stream; branches 1.. and every branch's side
+  // stream (complementary pipelining) belong to the batch
+  hipStream_t branch[kMaxBranches] = {};
+  hipStream_t side[kMaxBranches] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxBranches] = {};
+  hipEvent_t sfork[kMaxBranches] = {}, sjoin[kMaxBranches] = {};
 };
 
 namespace {
 
+// Key-switching jobs are kept in non-increasing level order, so a launch
+// group of consecutive jobs has a tight largest level.  Group g (B jobs)
+// runs on branch g mod S; the rescale jobs run on the last branch; all
+// branches fork from and join back to the launch stream.
 hipError_t batch_enqueue(ckks_batch* b, hipStream_t st) {
-  JobArg<KsJob> ka{};
-  ka.table = b->d_ks;
-  hipError_t e = ks_launch(*b->c, ka, b->n_ks, b->Lmax_ks, true, false, st);
+  const Ctx& c = *b->c;
+  const int S = b->plan.streams;
+  const int B = b->plan.jobs_per_launch > 0 ? std::min(b->plan.jobs_per_launch, b->n_ks) : b->n_ks;
+  auto on = [&](int br) { return br == 0 ? st : b->branch[br]; };
+  hipError_t e;
+  if (S > 1) {
+    if ((e = hipEventRecord(b->fork, st)) != hipSuccess) return e;
+    for (int br = 1; br < S; ++br)
+      if ((e = hipStreamWaitEvent(b->branch[br], b->fork, 0)) != hipSuccess) return e;
+  }
+  int group = 0;
+  for (int s0 = 0; s0 < b->n_ks; s0 += B, ++group) {
+    const int br = group % S;
+    JobArg<KsJob> ka{};
+    ka.table = b->d_ks + s0;
+    const KsSplit sp = b->plan.split ? KsSplit{b->side[br], b->sfork[br], b->sjoin[br]} : KsSplit{};
+    if ((e = ks_launch(c, ka, std::min(B, b->n_ks - s0), b->L_ks[s0], true, false, on(br), sp)) !=
+        hipSuccess)
+      return e;
+  }
+  if (b->n_rs) {
+    JobArg<RsJob> ra{};
+    ra.table = b->d_rs;
+    if ((e = rs_launch(c, ra, b->n_rs, b->Lmax_rs, on(S - 1))) != hipSuccess) return e;
+  }
+  if (S > 1) {
+    for (int br = 1; br < S; ++br) {
+      if ((e = hipEventRecord(b->join[br], b->branch[br])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(st, b->join[br], 0)) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+void batch_drop_graph(ckks_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+hipError_t batch_capture(ckks_batch* b) {
+  batch_drop_graph(b);
+  hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  JobArg<RsJob> ra{};
-  ra.table = b->d_rs;
-  return rs_launch(*b->c, ra, b->n_rs, b->Lmax_rs, st);
+  const hipError_t le = batch_enqueue(b, b->capture);
+  e = hipStreamEndCapture(b->capture, &b->graph);
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  return e;
 }
 
 void batch_free(ckks_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  batch_drop_graph(b);
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  for (int i = 0; i < kMaxBranches; ++i) {
+    if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
+    if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    if (b->sfork[i]) (void)hipEventDestroy(b->sfork[i]);
+    if (b->sjoin[i]) (void)hipEventDestroy(b->sjoin[i]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->d_ks) (void)hipFree(b->d_ks);
   if (b->d_rs) (void)hipFree(b->d_rs);
   if (b->d_ws) (void)hipFree(b->d_ws);
   delete b;
+}
+
+bool plan_ok(const ckks_batch_plan& p) {
+  return p.jobs_per_launch >= 0 && p.streams >= 1 && p.streams <= kMaxBranches &&
+         (p.split == 0 || p.split == 1);
 }
 
 }  // namespace
@@ -427,7 +500,9 @@ int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int*
     for (int t = 0; t < cnt; ++t)
       ja.inl[t] = KsJob{KS_HOIST, L, galois(c, h_rots[i0 + t]), 0, ct, M, h_rotks[i0 + t],
                         h_outs[i0 + t], job_ws[t]};
-    CKKS_TRY(ks_launch(c, ja, cnt, L, false, true, st), "hoisted rotations");
+    std::lock_guard<std::mutex> lk(c.side_mu);
+    CKKS_TRY(ks_launch(c, ja, cnt, L, false, true, st, KsSplit{c.side, c.fork_ev, c.join_ev}),
+             "hoisted rotations");
   }
   return CKKS_OK;
 }
@@ -456,7 +531,7 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
   std::vector<RsJob> rs;
   std::vector<size_t> ks_off, rs_off;
   size_t ws = 0;
-  int Lks = 0, Lrs = 0;
+  int Lrs = 0;
   for (int i = 0; i < n; ++i) {
     const ckks_job& j = h_jobs[i];
     const int lo = j.op == CKKS_JOB_RESCALE ? 2 : 1;
@@ -475,19 +550,25 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
                          j.op == CKKS_JOB_HMULT ? j.in1 : nullptr, j.key, j.out, nullptr});
       ks_off.push_back(ws);
       ws += round_up(ks_ws_words(c, j.L) * 4);
-      Lks = std::max(Lks, j.L);
     } else {
       return fail(CKKS_EINVAL, "job " + std::to_string(i) + ": unknown op");
     }
   }
+  // Non-increasing level order; jobs of one level that share a key are adjacent.
+  std::vector<int> order(ks.size());
+  for (size_t i = 0; i < ks.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (ks[x].L != ks[y].L) return ks[x].L > ks[y].L;
+    return ks[x].key < ks[y].key;
+  });
   DeviceGuard g(c.device);
   ckks_batch* b = new (std::nothrow) ckks_batch;
   if (!b) return fail(CKKS_ENOMEM, "host allocation failed");
   b->c = &c;
   b->n_ks = (int)ks.size();
   b->n_rs = (int)rs.size();
-  b->Lmax_ks = Lks;
   b->Lmax_rs = Lrs;
+  b->use_graph = use_graph != 0;
   const size_t tab = round_up(sizeof(KsJob) * ks.size()) + round_up(sizeof(RsJob) * rs.size());
   if (hipMalloc(&b->d_ws, ws) != hipSuccess ||
       (!ks.empty() && hipMalloc(&b->d_ks, sizeof(KsJob) * ks.size()) != hipSuccess) ||
@@ -496,22 +577,32 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
     return fail(CKKS_ENOMEM, "device allocation for the batch failed");
   }
   b->bytes = ws + tab;
-  for (size_t i = 0; i < ks.size(); ++i) ks[i].ws = (uint32_t*)((char*)b->d_ws + ks_off[i]);
+  std::vector<KsJob> sorted;
+  for (int i : order) {
+    sorted.push_back(ks[i]);
+    sorted.back().ws = (uint32_t*)((char*)b->d_ws + ks_off[i]);
+    b->L_ks.push_back(ks[i].L);
+  }
   for (size_t i = 0; i < rs.size(); ++i) rs[i].ws = (uint32_t*)((char*)b->d_ws + rs_off[i]);
-  if ((!ks.empty() && hipMemcpy(b->d_ks, ks.data(), sizeof(KsJob) * ks.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+  if ((!ks.empty() && hipMemcpy(b->d_ks, sorted.data(), sizeof(KsJob) * ks.size(), hipMemcpyHostToDevice) != hipSuccess) ||
       (!rs.empty() && hipMemcpy(b->d_rs, rs.data(), sizeof(RsJob) * rs.size(), hipMemcpyHostToDevice) != hipSuccess)) {
     batch_free(b);
     return fail(CKKS_EHIP, "copying the job table failed");
   }
-  if (use_graph) {
+  bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < kMaxBranches; ++i)
+    ok = (i == 0 || hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking) == hipSuccess) &&
+         hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&b->sfork[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&b->sjoin[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    batch_free(b);
+    return fail(CKKS_EHIP, "creating the batch's streams / events failed");
+  }
+  if (b->use_graph) {
     hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      const hipError_t le = batch_enqueue(b, b->capture);
-      e = hipStreamEndCapture(b->capture, &b->graph);
-      if (le != hipSuccess) e = le;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = batch_capture(b);
     if (e != hipSuccess) {
       batch_free(b);
       return hip_fail(e, "capturing the batch graph");
@@ -532,6 +623,75 @@ int ckks_batch_launch(ckks_batch* b, void* stream) {
   return CKKS_OK;
 }
 
+int ckks_batch_get_plan(const ckks_batch* b, ckks_batch_plan* plan) {
+  if (!b || !plan) return fail(CKKS_EINVAL, "null argument");
+  *plan = b->plan;
+  return CKKS_OK;
+}
+
+int ckks_batch_set_plan(ckks_batch* b, const ckks_batch_plan* plan) {
+  if (!b || !plan) return fail(CKKS_EINVAL, "null argument");
+  if (!plan_ok(*plan))
+    return fail(CKKS_EINVAL, "plan needs jobs_per_launch >= 0, 1 <= streams <= 4, split in {0, 1}");
+  DeviceGuard g(b->c->device);
+  b->plan = *plan;
+  b->plan.reserved = 0;
+  if (b->use_graph) CKKS_TRY(batch_capture(b), "re-capturing the batch graph");
+  return CKKS_OK;
+}
+
+int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best, float* best_us) {
+  if (!b || reps < 1 || reps > 1000) return fail(CKKS_EINVAL, "need a batch and 1 <= reps <= 1000");
+  DeviceGuard g(b->c->device);
+  const hipStream_t st = (hipStream_t)stream;
+  std::vector<int> sizes{0};
+  for (int B : {32, 16, 8, 4, 2})
+    if (B < b->n_ks) sizes.push_back(B);
+  hipEvent_t t0, t1;
+  CKKS_TRY(hipEventCreate(&t0), "hipEventCreate");
+  if (hipEventCreate(&t1) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return fail(CKKS_EHIP, "hipEventCreate failed");
+  }
+  const ckks_batch_plan start = b->plan;
+  ckks_batch_plan top = start;
+  float top_us = -1.f;
+  hipError_t e = hipSuccess;
+  for (int B : sizes) {
+    const int groups = B ? (b->n_ks + B - 1) / B : 1;
+    for (int S = 1; S <= kMaxBranches && e == hipSuccess; ++S) {
+      if (S > 1 && S > groups + (b->n_rs ? 1 : 0)) break;
+      for (int split = 0; split <= 1 && e == hipSuccess; ++split) {
+        b->plan = ckks_batch_plan{B, S, split, 0};
+        if (b->use_graph && (e = batch_capture(b)) != hipSuccess) break;
+        auto launch = [&]() { return b->exec ? hipGraphLaunch(b->exec, st) : batch_enqueue(b, st); };
+        if ((e = launch()) != hipSuccess) break;  // warm-up
+        if ((e = hipEventRecord(t0, st)) != hipSuccess) break;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+        if (e != hipSuccess || (e = hipEventRecord(t1, st)) != hipSuccess ||
+            (e = hipEventSynchronize(t1)) != hipSuccess)
+          break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+        const float us = 1e3f * ms / reps;
+        if (top_us < 0.f || us < top_us) {
+          top_us = us;
+          top = b->plan;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  b->plan = e == hipSuccess ? top : start;
+  const hipError_t ce = b->use_graph ? batch_capture(b) : hipSuccess;
+  if (e != hipSuccess) return hip_fail(e, "timing candidate plans");
+  if (ce != hipSuccess) return hip_fail(ce, "re-capturing the batch graph");
+  if (best) *best = top;
+  if (best_us) *best_us = top_us;
+  return CKKS_OK;
+}
+
 size_t ckks_batch_device_bytes(const ckks_batch* b) { return b ? b->bytes : 0; }
 
 int ckks_batch_destroy(ckks_batch* b) {
@@ -543,7 +703,7 @@ int ckks_batch_destroy(ckks_batch* b) {
 
 int ckks_trace_begin(ckks_ctx* ctx, int stage, int capacity) {
   if (!ctx) return fail(CKKS_EINVAL, "null context");
-  if (stage < CKKS_STAGE_INTT_BLOCKS || stage > CKKS_STAGE_RESCALE_NTT || capacity < 1)
+  if (stage < CKKS_STAGE_INTT_BLOCKS || stage > CKKS_STAGE_NTT_IP_P || capacity < 1)
     return fail(CKKS_EINVAL, "bad trace stage or capacity");
   Ctx& c = ctx->c;
   if (c.trace.stage) return fail(CKKS_EINVAL, "a trace is already armed on this context");

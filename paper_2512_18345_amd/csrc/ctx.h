@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -97,6 +98,12 @@ struct Ctx {
   uint2* d_pinv = nullptr;            // [L_max]
   // Rescale at level L: q_{L-1}^-1 mod q_i (Shoup), i < L - 1.
   uint2* d_rescale_inv = nullptr;     // [L_max + 1][L_max]
+
+  // complementary pipelining: a side stream and fork / join events shared by
+  // the single-call entry points and batches of this context (serialised)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  mutable std::mutex side_mu;
 
   // kernel tracing (ckks_trace_begin / ckks_trace_end)
   struct Trace {

@@ -42,6 +42,16 @@ struct __align__(16) RsJob {
 
 constexpr int kInlineJobs = 16;
 
+// Rows of the key inner product a K5 launch covers.
+enum KsPart : int { KS_PART_ALL = 0, KS_PART_P = 1, KS_PART_Q = 2 };
+
+// Complementary pipelining resources: a side stream and two events (fork,
+// join).  side == nullptr runs the pipeline on one stream.
+struct KsSplit {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 // Jobs either inline in the kernel arguments (n <= kInlineJobs) or in a device
 // table written only by the host.  get() returns the job by value through
 // scalar loads, so every field is work-group uniform.
@@ -63,7 +73,7 @@ size_t rs_ws_words(const Ctx& c, int L);
 // Lmax.  with_modup: some job is not KS_HOIST (stage 1 runs); with_hoist: some
 // job is KS_HOIST.
 hipError_t ks_launch(const Ctx& c, const JobArg<KsJob>& jobs, int njobs, int Lmax, bool with_modup,
-                     bool with_hoist, hipStream_t st);
+                     bool with_hoist, hipStream_t st, const KsSplit& sp = KsSplit{});
 // Enqueue rescale (drop the top prime) for njobs jobs.
 hipError_t rs_launch(const Ctx& c, const JobArg<RsJob>& jobs, int njobs, int Lmax, hipStream_t st);
 

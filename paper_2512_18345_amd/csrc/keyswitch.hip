@@ -228,13 +228,13 @@ __global__ __launch_bounds__(kWG) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) 
 // HOIST selects the variant for hoisted-rotation jobs (gather of sigma(M), no
 // transform); the other variant serves every other job kind.
 template <int LOGN1, bool HOIST>
-__global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> JA) {
+__global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> JA, int part) {
   const KsJob J = JA.get(blockIdx.z);
   const int logN = K.T.logN;
   const size_t N = (size_t)1 << logN;
   const KsView V = ks_view(J, K, N);
-  const int r = blockIdx.y;
-  if (r >= V.R || (J.kind == KS_HOIST) != HOIST) return;
+  const int r = blockIdx.y + (part == KS_PART_P ? V.L : 0);
+  if (r >= V.R || (part == KS_PART_Q && r >= V.L) || (J.kind == KS_HOIST) != HOIST) return;
   __shared__ __align__(16) uint32_t s[kLds];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
   const ModC m = ldc(K.T.mod + pi);
@@ -342,13 +342,13 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
 // once), then the inner product runs one 16-byte quad at a time, so the
 // 64-bit accumulators never hold more than four elements per component.
 template <int LOGN1, int NB>
-__global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> JA) {
+__global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> JA, int part) {
   const KsJob J = JA.get(blockIdx.z);
   const int logN = K.T.logN;
   const size_t N = (size_t)1 << logN;
   const KsView V = ks_view(J, K, N);
-  const int r = blockIdx.y;
-  if (r >= V.R || J.kind == KS_HOIST) return;
+  const int r = blockIdx.y + (part == KS_PART_P ? V.L : 0);
+  if (r >= V.R || (part == KS_PART_Q && r >= V.L) || J.kind == KS_HOIST) return;
   __shared__ __align__(16) uint32_t s[NB * kLds];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
   const ModC m = ldc(K.T.mod + pi);
@@ -772,7 +772,7 @@ hipError_t small_dispatch(int v, dim3 g, hipStream_t st, const KsConst& K, const
 
 template <int L1>
 hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs, int njobs,
-                       int Lmax, bool with_modup, bool with_hoist, hipStream_t st) {
+                       int Lmax, bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp) {
   const int Rmax = Lmax + c.k;
   const int tiles = c.N / kTile;
   const int cols = c.N / kWG;
@@ -794,17 +794,48 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     c.trace_pre(CKKS_STAGE_NTT_COLS_UP, st);
     k4_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), kWG, 0, st>>>(K, jobs);
     c.trace_post(CKKS_STAGE_NTT_COLS_UP, st);
-    c.trace_pre(CKKS_STAGE_NTT_IP, st);
-    const dim3 g5(tiles, Rmax, njobs);
-    switch (std::max(c.beta_max(), 2)) {
-      case 2: k5s_ntt_blks_ip<L1, 2><<<g5, kWG, 0, st>>>(K, jobs); break;
-      case 3: k5s_ntt_blks_ip<L1, 3><<<g5, kWG, 0, st>>>(K, jobs); break;
-      case 4: k5s_ntt_blks_ip<L1, 4><<<g5, kWG, 0, st>>>(K, jobs); break;
-      default: k5_ntt_blks_ip<L1, false><<<g5, kWG, 0, st>>>(K, jobs); break;
-    }
-    c.trace_post(CKKS_STAGE_NTT_IP, st);
   }
-  if (with_hoist) k5_ntt_blks_ip<L1, true><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs);
+  // Stage 2.  With a side stream, complementary pipelining (Sec. IV-B): the
+  // inner product of the P rows runs first on st, and ModDown's P-row chain
+  // (K6..K8, ALU-heavy) overlaps with the Q-row inner product on the side
+  // stream (key streaming, HBM-heavy); K9 joins both.
+  auto k5 = [&](int part, hipStream_t s5, int rows) {
+    const dim3 g5(tiles, rows, njobs);
+    switch (std::max(c.beta_max(), 2)) {
+      case 2: k5s_ntt_blks_ip<L1, 2><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
+      case 3: k5s_ntt_blks_ip<L1, 3><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
+      case 4: k5s_ntt_blks_ip<L1, 4><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
+      default: k5_ntt_blks_ip<L1, false><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
+    }
+  };
+  const bool split = sp.side != nullptr;
+  if (split) {
+    if ((e = hipEventRecord(sp.fork, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(sp.side, sp.fork, 0)) != hipSuccess) return e;
+  }
+  if (with_modup) {
+    if (split) {
+      c.trace_pre(CKKS_STAGE_NTT_IP, sp.side);
+      k5(KS_PART_Q, sp.side, Lmax);
+      c.trace_post(CKKS_STAGE_NTT_IP, sp.side);
+      c.trace_pre(CKKS_STAGE_NTT_IP_P, st);
+      k5(KS_PART_P, st, c.k);
+      c.trace_post(CKKS_STAGE_NTT_IP_P, st);
+    } else {
+      c.trace_pre(CKKS_STAGE_NTT_IP, st);
+      k5(KS_PART_ALL, st, Rmax);
+      c.trace_post(CKKS_STAGE_NTT_IP, st);
+    }
+  }
+  if (with_hoist) {
+    if (split) {
+      k5_ntt_blks_ip<L1, true><<<dim3(tiles, Lmax, njobs), kWG, 0, sp.side>>>(K, jobs, KS_PART_Q);
+      k5_ntt_blks_ip<L1, true><<<dim3(tiles, c.k, njobs), kWG, 0, st>>>(K, jobs, KS_PART_P);
+    } else {
+      k5_ntt_blks_ip<L1, true><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs, KS_PART_ALL);
+    }
+  }
+  if (split && (e = hipEventRecord(sp.join, sp.side)) != hipSuccess) return e;
   c.trace_pre(CKKS_STAGE_INTT_COLS_P, st);
   k6_intt_cols_p<L1><<<dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), kWG, 0, st>>>(K, jobs);
   c.trace_post(CKKS_STAGE_INTT_COLS_P, st);
@@ -815,6 +846,7 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   c.trace_pre(CKKS_STAGE_NTT_COLS_DOWN, st);
   k8_ntt_cols_w<L1><<<dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
   c.trace_post(CKKS_STAGE_NTT_COLS_DOWN, st);
+  if (split && (e = hipStreamWaitEvent(st, sp.join, 0)) != hipSuccess) return e;
   c.trace_pre(CKKS_STAGE_NTT_COMBINE, st);
   k9_ntt_blks_combine<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
   c.trace_post(CKKS_STAGE_NTT_COMBINE, st);
@@ -836,15 +868,15 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
 }  // namespace
 
 hipError_t ks_launch(const Ctx& c, const JobArg<KsJob>& jobs, int njobs, int Lmax, bool with_modup,
-                     bool with_hoist, hipStream_t st) {
+                     bool with_hoist, hipStream_t st, const KsSplit& sp) {
   if (njobs <= 0) return hipSuccess;
   const KsConst K = make_const(c);
   switch (c.logN - kBlockLog) {
-    case 4: return ks_launch_t<4>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
-    case 5: return ks_launch_t<5>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
-    case 6: return ks_launch_t<6>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
-    case 7: return ks_launch_t<7>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
-    case 8: return ks_launch_t<8>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st);
+    case 4: return ks_launch_t<4>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 5: return ks_launch_t<5>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 6: return ks_launch_t<6>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 7: return ks_launch_t<7>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 8: return ks_launch_t<8>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
     default: return hipErrorInvalidValue;
   }
 }

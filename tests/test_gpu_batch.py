@@ -101,3 +101,42 @@ def test_batch_job_against_oracle():
         assert not msg, msg
     finally:
         P.ckks_batch_destroy(b)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_every_plan_gives_the_single_call_results(use_graph):
+    """Launch groups, concurrent branches and the split inner product change
+    only the schedule: each plan must reproduce the single calls bitwise."""
+    spec = ci.get("n16_l36")
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(spec.seed + 200)
+    keys = [dev(rng.evk(spec)) for _ in range(2)]
+    n = 11
+    levels = rng.integers(1, spec.L_max + 1, n)
+    jobs, singles = _make_jobs(spec, ctx, rng, n, levels, keys)
+    want = [_single(ctx, *s) for s in singles]
+    b = P.ckks_batch_create(ctx.handle, jobs, use_graph=use_graph)
+    try:
+        assert P.ckks_batch_get_plan(b) == dict(jobs_per_launch=0, streams=1, split=1)
+        for plan in [(0, 1, 0), (0, 2, 1), (1, 4, 1), (2, 3, 0), (3, 2, 1), (8, 1, 1)]:
+            P.ckks_batch_set_plan(b, *plan)
+            assert P.ckks_batch_get_plan(b) == dict(zip(("jobs_per_launch", "streams", "split"), plan))
+            for rep in range(2):
+                for j in jobs:
+                    j["out"].fill_(-1)
+                P.ckks_batch_launch(b)
+                torch.cuda.synchronize()
+                for i, j in enumerate(jobs):
+                    msg = first_mismatch(host(j["out"]), want[i])
+                    assert not msg, f"plan {plan} replay {rep}, job {i} ({singles[i][0]}, L={singles[i][1]}): {msg}"
+        plan, us = P.ckks_batch_tune(b, reps=1)
+        assert us > 0 and plan == P.ckks_batch_get_plan(b)
+        for j in jobs:
+            j["out"].fill_(-1)
+        P.ckks_batch_launch(b)
+        torch.cuda.synchronize()
+        for i, j in enumerate(jobs):
+            msg = first_mismatch(host(j["out"]), want[i])
+            assert not msg, f"tuned plan {plan}, job {i}: {msg}"
+    finally:
+        P.ckks_batch_destroy(b)
