@@ -277,7 +277,8 @@ int ckks_batch_launch(ckks_batch *batch, void *stream);
  * overlap on the device; split = 1 runs the Q-row inner product of each
  * group on a side stream beside the P-row ModDown chain (Sec. IV-B).
  * Rescale jobs run on the last branch.  Every plan gives bitwise the same
- * results.  Default {0, 1, 1}.
+ * results.  Default {0, 1, 1}.  A batch created with use_graph runs one
+ * branch (streams = 1): a multi-branch launch sequence is not captured.
  */
 typedef struct ckks_batch_plan {
     int jobs_per_launch;  /* >= 0 */
@@ -287,12 +288,14 @@ typedef struct ckks_batch_plan {
 } ckks_batch_plan;
 
 int ckks_batch_get_plan(const ckks_batch *batch, ckks_batch_plan *plan);
-/* Replace the plan (re-captures the graph of a graph batch).  Synchronous
- * for graph batches; must not overlap a launch of the same batch. */
+/* Replace the plan (re-captures the graph of a graph batch).  Must not
+ * overlap a launch of the same batch.  Errors: CKKS_EINVAL (bad plan),
+ * CKKS_EUNSUPPORTED (streams > 1 on a graph batch), CKKS_EHIP. */
 int ckks_batch_set_plan(ckks_batch *batch, const ckks_batch_plan *plan);
 /*
  * Autotuner: times candidate plans (jobs_per_launch in {all, 32, 16, 8, 4, 2}
- * below the job count, streams 1..4 up to the number of groups, split 0/1),
+ * below the job count, streams 1..4 up to the number of groups (1 for a
+ * graph batch), split 0/1),
  * each as one warm-up launch then `reps` launches between two events on
  * `stream`, and keeps the fastest (graph batches are re-captured and timed as
  * graph launches).  Runs the batch up to 48 x (reps + 1) times and

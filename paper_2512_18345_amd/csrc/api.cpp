@@ -194,7 +194,7 @@ struct ckks_batch {
   hipStream_t side[kMaxBranches] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kMaxBranches] = {};
-  hipEvent_t sfork[kMaxBranches] = {}, sjoin[kMaxBranches] = {};
+  std::vector<hipEvent_t> gev;  // fork / join events of the split, two per launch group
 };
 
 namespace {
@@ -219,7 +219,9 @@ hipError_t batch_enqueue(ckks_batch* b, hipStream_t st) {
     const int br = group % S;
     JobArg<KsJob> ka{};
     ka.table = b->d_ks + s0;
-    const KsSplit sp = b->plan.split ? KsSplit{b->side[br], b->sfork[br], b->sjoin[br]} : KsSplit{};
+    if (b->plan.split && b->gev.size() < 2 * (size_t)group + 2) return hipErrorInvalidValue;
+    const KsSplit sp =
+        b->plan.split ? KsSplit{b->side[br], b->gev[2 * group], b->gev[2 * group + 1]} : KsSplit{};
     if ((e = ks_launch(c, ka, std::min(B, b->n_ks - s0), b->L_ks[s0], true, false, on(br), sp)) !=
         hipSuccess)
       return e;
@@ -234,6 +236,25 @@ hipError_t batch_enqueue(ckks_batch* b, hipStream_t st) {
       if ((e = hipEventRecord(b->join[br], b->branch[br])) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(st, b->join[br], 0)) != hipSuccess) return e;
     }
+  }
+  return hipSuccess;
+}
+
+int batch_groups(const ckks_batch* b, const ckks_batch_plan& p) {
+  if (b->n_ks == 0) return 0;
+  const int B = p.jobs_per_launch > 0 ? std::min(p.jobs_per_launch, b->n_ks) : b->n_ks;
+  return (b->n_ks + B - 1) / B;
+}
+
+// Two events per launch group, so no event is recorded twice in one launch
+// sequence (in particular not inside one graph capture).
+hipError_t batch_events(ckks_batch* b, const ckks_batch_plan& p) {
+  const size_t need = 2 * (size_t)batch_groups(b, p);
+  while (b->gev.size() < need) {
+    hipEvent_t ev;
+    const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    b->gev.push_back(ev);
   }
   return hipSuccess;
 }
@@ -263,9 +284,8 @@ void batch_free(ckks_batch* b) {
     if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
     if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
     if (b->join[i]) (void)hipEventDestroy(b->join[i]);
-    if (b->sfork[i]) (void)hipEventDestroy(b->sfork[i]);
-    if (b->sjoin[i]) (void)hipEventDestroy(b->sjoin[i]);
   }
+  for (hipEvent_t ev : b->gev) (void)hipEventDestroy(ev);
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->d_ks) (void)hipFree(b->d_ks);
   if (b->d_rs) (void)hipFree(b->d_rs);
@@ -593,9 +613,8 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
   for (int i = 0; ok && i < kMaxBranches; ++i)
     ok = (i == 0 || hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking) == hipSuccess) &&
          hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&b->sfork[i], hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&b->sjoin[i], hipEventDisableTiming) == hipSuccess;
+         hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) == hipSuccess;
+  ok = ok && batch_events(b, b->plan) == hipSuccess;
   if (!ok) {
     batch_free(b);
     return fail(CKKS_EHIP, "creating the batch's streams / events failed");
@@ -633,7 +652,10 @@ int ckks_batch_set_plan(ckks_batch* b, const ckks_batch_plan* plan) {
   if (!b || !plan) return fail(CKKS_EINVAL, "null argument");
   if (!plan_ok(*plan))
     return fail(CKKS_EINVAL, "plan needs jobs_per_launch >= 0, 1 <= streams <= 4, split in {0, 1}");
+  if (b->use_graph && plan->streams > 1)
+    return fail(CKKS_EUNSUPPORTED, "a graph batch runs one branch (streams = 1)");
   DeviceGuard g(b->c->device);
+  CKKS_TRY(batch_events(b, *plan), "creating the batch's events");
   b->plan = *plan;
   b->plan.reserved = 0;
   if (b->use_graph) CKKS_TRY(batch_capture(b), "re-capturing the batch graph");
@@ -657,9 +679,11 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
   ckks_batch_plan top = start;
   float top_us = -1.f;
   hipError_t e = hipSuccess;
+  const int max_streams = b->use_graph ? 1 : kMaxBranches;
   for (int B : sizes) {
     const int groups = B ? (b->n_ks + B - 1) / B : 1;
-    for (int S = 1; S <= kMaxBranches && e == hipSuccess; ++S) {
+    if ((e = batch_events(b, ckks_batch_plan{B, 1, 1, 0})) != hipSuccess) break;
+    for (int S = 1; S <= max_streams && e == hipSuccess; ++S) {
       if (S > 1 && S > groups + (b->n_rs ? 1 : 0)) break;
       for (int split = 0; split <= 1 && e == hipSuccess; ++split) {
         b->plan = ckks_batch_plan{B, S, split, 0};
