@@ -30,7 +30,7 @@ LIMB_BYTES = 4  # uint32 residues
 # key-switching kernels.
 KERNEL_SOURCES = ["paper_2512_18345_amd/csrc/" + f for f in
                   ("keyswitch.hip", "keyswitch.h", "ntt_tile.h", "arith.h", "ctx.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k5s_ntt_blks_ip_q_rows_n16_l36_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k5s_ntt_blks_ip_n16_l36_traffic.txt")
 
 
 def kernel_source_hash() -> str:
@@ -154,10 +154,9 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # Dominant kernel: NTT block pass fused with the key inner product over the
-    # L ciphertext-modulus rows (stage 2 of key-switching; it runs on the
-    # context's side stream, beside the P-row ModDown chain), timed by events
-    # around each of its launches on that stream, inside the timed region.
+    # Dominant kernel: NTT block pass fused with the key inner product (stage 2
+    # of key-switching), timed by events around each of its launches on the
+    # stream it runs on, inside the timed region.
     ip_launches = 2 * args.steps
     P.ckks_trace_begin(h, P.STAGE["NTT_IP"], ip_launches)
     t0 = time.perf_counter()
@@ -185,13 +184,13 @@ def main():
     beta = ctx.beta(L)
     R = L + k
     limb = N * LIMB_BYTES
-    # per launch (the L ciphertext-modulus rows): beta*L ModUp rows in,
-    # 2*beta*L key rows in, 2*L accumulator rows out
-    ip_bytes = (3 * beta + 2) * L * limb
+    # per launch: the beta*R ModUp rows in, the 2*beta*R key rows in, the 2*R
+    # accumulator rows out
+    ip_bytes = (3 * beta + 2) * R * limb
     ip_us = 1e3 * float(np.mean(ip_ms))
     achieved = ip_bytes / (ip_us * 1e-6) / 1e9
     roofline = {
-        "kernel": "k5s_ntt_blks_ip (Q rows)",
+        "kernel": "k5s_ntt_blks_ip",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": 8000.0,
@@ -277,7 +276,9 @@ def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
         default = timed(lambda: P.ckks_batch_launch(b, stream), n_ks)
         plan, _ = P.ckks_batch_tune(b, 2, stream)
         tuned = timed(lambda: P.ckks_batch_launch(b, stream), n_ks)
-        return default, tuned, plan
+        log = [[p["jobs_per_launch"], p["streams"], p["split"], round(us, 1)]
+               for p, us in P.ckks_batch_tune_log(b)]
+        return default, tuned, dict(plan, candidates_B_S_split_us=log)
 
     # (a) same work, batched vs single-op
     outs = [torch.empty((2, L, N), dtype=torch.int32, device="cuda") for _ in range(8)]

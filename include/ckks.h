@@ -274,8 +274,10 @@ int ckks_batch_launch(ckks_batch *batch, void *stream);
  * adjacent); consecutive groups of jobs_per_launch of them (0 = all) each
  * run the pipeline once, group g on branch g mod streams; branches are
  * streams forked from and joined back to the launch stream, so groups
- * overlap on the device; split = 1 runs the Q-row inner product of each
- * group on a side stream beside the P-row ModDown chain (Sec. IV-B).
+ * overlap on the device; split != 0 runs the Q-row inner product of each
+ * group on a side stream (Sec. IV-B complementary pipelining): split = 1
+ * starts it beside the P-row inner product, split = 2 after it, so that it
+ * overlaps only the P-row ModDown chain.
  * Rescale jobs run on the last branch.  Every plan gives bitwise the same
  * results.  Default {0, 1, 1}.  A batch created with use_graph runs one
  * branch (streams = 1): a multi-branch launch sequence is not captured.
@@ -283,7 +285,7 @@ int ckks_batch_launch(ckks_batch *batch, void *stream);
 typedef struct ckks_batch_plan {
     int jobs_per_launch;  /* >= 0 */
     int streams;          /* 1..4 */
-    int split;            /* 0 or 1 */
+    int split;            /* 0, 1 or 2 */
     int reserved;
 } ckks_batch_plan;
 
@@ -295,16 +297,21 @@ int ckks_batch_set_plan(ckks_batch *batch, const ckks_batch_plan *plan);
 /*
  * Autotuner: times candidate plans (jobs_per_launch in {all, 32, 16, 8, 4, 2}
  * below the job count, streams 1..4 up to the number of groups (1 for a
- * graph batch), split 0/1),
+ * graph batch), split 0/1/2),
  * each as one warm-up launch then `reps` launches between two events on
  * `stream`, and keeps the fastest (graph batches are re-captured and timed as
- * graph launches).  Runs the batch up to 48 x (reps + 1) times and
+ * graph launches).  Runs the batch up to 72 x (reps + 1) times and
  * synchronises `stream`: outputs are written, inputs only read.  best /
  * best_us (either may be NULL) receive the chosen plan and its time per
  * launch in microseconds.  On error the previous plan is kept.
  */
 int ckks_batch_tune(ckks_batch *batch, int reps, void *stream, ckks_batch_plan *best,
                     float *best_us);
+/* The candidates of the last ckks_batch_tune and their microseconds per
+ * launch, in the order tried: *n receives their number, the first
+ * min(cap, *n) are copied to plans / us. */
+int ckks_batch_tune_log(const ckks_batch *batch, ckks_batch_plan *plans, float *us, int cap,
+                        int *n);
 /* Device bytes the batch holds (tables + scratch). */
 size_t ckks_batch_device_bytes(const ckks_batch *batch);
 int ckks_batch_destroy(ckks_batch *batch);
@@ -353,10 +360,10 @@ int ckks_server_times(ckks_server *server, uint64_t first, int n, double *h_subm
 int ckks_server_destroy(ckks_server *server);
 
 /*
- * Kernel tracing.  Between ckks_trace_begin and ckks_trace_end, every launch
- * of pipeline stage `stage` (CKKS_STAGE_*) by this context is bracketed by a
- * pair of HIP events recorded on the launch's own stream, for the first
- * `capacity` launches.  ckks_trace_end waits for the last recorded event,
+ * Kernel tracing.  Between ckks_trace_begin and ckks_trace_end, every kernel
+ * launch of pipeline stage `stage` (CKKS_STAGE_*) by this context carries a
+ * pair of HIP events that the runtime records at the start and the end of
+ * that dispatch (hipExtLaunchKernel), for the first `capacity` launches.  ckks_trace_end waits for the last recorded event,
  * writes the per-launch durations in milliseconds to h_ms (capacity floats,
  * may be NULL) and the number of recorded launches to *count, and disarms.
  * The events are created in ckks_trace_begin and destroyed in ckks_trace_end.

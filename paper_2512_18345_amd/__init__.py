@@ -20,7 +20,7 @@ __all__ = [
     "ckks_hrot", "ckks_hrot_hoisted", "ckks_rescale", "ckks_trace_begin", "ckks_trace_end", "STAGE",
     "JOB", "ckks_job", "ckks_batch_create", "ckks_batch_launch", "ckks_batch_device_bytes",
     "ckks_batch_destroy", "ckks_batch_plan", "ckks_batch_get_plan", "ckks_batch_set_plan",
-    "ckks_batch_tune", "ckks_stats", "ckks_server_create", "ckks_server_submit",
+    "ckks_batch_tune", "ckks_batch_tune_log", "ckks_stats", "ckks_server_create", "ckks_server_submit",
     "ckks_server_poll", "ckks_server_drain", "ckks_server_stats", "ckks_server_times",
     "ckks_server_destroy", "ckks_pmult_sum", "ckks_add",
 ]
@@ -99,6 +99,7 @@ _SIGS = {
     "ckks_batch_get_plan": [_vp, _vp],
     "ckks_batch_set_plan": [_vp, _vp],
     "ckks_batch_tune": [_vp, _i, _vp, _vp, _vp],
+    "ckks_batch_tune_log": [_vp, _vp, _vp, _i, ctypes.POINTER(_i)],
     "ckks_pmult_sum": [_vp, _vp, _vp, _i, _i, _vp, _vp],
     "ckks_add": [_vp, _vp, _vp, _i, _vp, _vp],
     "ckks_server_create": [_vp, _i, _sz, _i, ctypes.POINTER(_vp)],
@@ -282,6 +283,17 @@ def ckks_batch_get_plan(batch) -> dict:
 def ckks_batch_set_plan(batch, jobs_per_launch=0, streams=1, split=1):
     p = ckks_batch_plan(int(jobs_per_launch), int(streams), int(split), 0)
     _check(lib().ckks_batch_set_plan(batch, ctypes.cast(ctypes.byref(p), _vp)))
+
+
+def ckks_batch_tune_log(batch) -> list:
+    """[(plan dict, microseconds per launch)] of the last ckks_batch_tune."""
+    n = _i()
+    _check(lib().ckks_batch_tune_log(batch, None, None, 0, ctypes.byref(n)))
+    plans = (ckks_batch_plan * max(n.value, 1))()
+    us = (ctypes.c_float * max(n.value, 1))()
+    _check(lib().ckks_batch_tune_log(batch, ctypes.cast(plans, _vp), ctypes.cast(us, _vp), n.value,
+                                     ctypes.byref(n)))
+    return [(plans[i].as_dict(), float(us[i])) for i in range(n.value)]
 
 
 def ckks_batch_tune(batch, reps=3, stream=None):

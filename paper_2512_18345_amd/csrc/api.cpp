@@ -160,9 +160,7 @@ int run_one(const Ctx& c, int kind, int L, uint32_t gal, const uint32_t* a, cons
   JobArg<KsJob> ja{};
   ja.table = nullptr;
   ja.inl[0] = KsJob{kind, L, gal, 0, a, b, key, out, (uint32_t*)ws};
-  std::lock_guard<std::mutex> lk(c.side_mu);
-  CKKS_TRY(ks_launch(c, ja, 1, L, true, false, st, KsSplit{c.side, c.fork_ev, c.join_ev}),
-           "key-switching pipeline");
+  CKKS_TRY(ks_launch(c, ja, 1, L, true, false, st), "key-switching pipeline");
   return CKKS_OK;
 }
 
@@ -195,6 +193,7 @@ struct ckks_batch {
   hipEvent_t fork = nullptr;
   hipEvent_t join[kMaxBranches] = {};
   std::vector<hipEvent_t> gev;  // fork / join events of the split, two per launch group
+  std::vector<std::pair<ckks_batch_plan, float>> tune_log;  // last ckks_batch_tune: plan, us
 };
 
 namespace {
@@ -220,8 +219,9 @@ hipError_t batch_enqueue(ckks_batch* b, hipStream_t st) {
     JobArg<KsJob> ka{};
     ka.table = b->d_ks + s0;
     if (b->plan.split && b->gev.size() < 2 * (size_t)group + 2) return hipErrorInvalidValue;
-    const KsSplit sp =
-        b->plan.split ? KsSplit{b->side[br], b->gev[2 * group], b->gev[2 * group + 1]} : KsSplit{};
+    const KsSplit sp = b->plan.split
+                           ? KsSplit{b->side[br], b->gev[2 * group], b->gev[2 * group + 1], b->plan.split == 2}
+                           : KsSplit{};
     if ((e = ks_launch(c, ka, std::min(B, b->n_ks - s0), b->L_ks[s0], true, false, on(br), sp)) !=
         hipSuccess)
       return e;
@@ -294,8 +294,8 @@ void batch_free(ckks_batch* b) {
 }
 
 bool plan_ok(const ckks_batch_plan& p) {
-  return p.jobs_per_launch >= 0 && p.streams >= 1 && p.streams <= kMaxBranches &&
-         (p.split == 0 || p.split == 1);
+  return p.jobs_per_launch >= 0 && p.streams >= 1 && p.streams <= kMaxBranches && p.split >= 0 &&
+         p.split <= 2;
 }
 
 }  // namespace
@@ -520,9 +520,7 @@ int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int*
     for (int t = 0; t < cnt; ++t)
       ja.inl[t] = KsJob{KS_HOIST, L, galois(c, h_rots[i0 + t]), 0, ct, M, h_rotks[i0 + t],
                         h_outs[i0 + t], job_ws[t]};
-    std::lock_guard<std::mutex> lk(c.side_mu);
-    CKKS_TRY(ks_launch(c, ja, cnt, L, false, true, st, KsSplit{c.side, c.fork_ev, c.join_ev}),
-             "hoisted rotations");
+    CKKS_TRY(ks_launch(c, ja, cnt, L, false, true, st), "hoisted rotations");
   }
   return CKKS_OK;
 }
@@ -651,7 +649,7 @@ int ckks_batch_get_plan(const ckks_batch* b, ckks_batch_plan* plan) {
 int ckks_batch_set_plan(ckks_batch* b, const ckks_batch_plan* plan) {
   if (!b || !plan) return fail(CKKS_EINVAL, "null argument");
   if (!plan_ok(*plan))
-    return fail(CKKS_EINVAL, "plan needs jobs_per_launch >= 0, 1 <= streams <= 4, split in {0, 1}");
+    return fail(CKKS_EINVAL, "plan needs jobs_per_launch >= 0, 1 <= streams <= 4, split in {0, 1, 2}");
   if (b->use_graph && plan->streams > 1)
     return fail(CKKS_EUNSUPPORTED, "a graph batch runs one branch (streams = 1)");
   DeviceGuard g(b->c->device);
@@ -677,6 +675,7 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
   }
   const ckks_batch_plan start = b->plan;
   ckks_batch_plan top = start;
+  b->tune_log.clear();
   float top_us = -1.f;
   hipError_t e = hipSuccess;
   const int max_streams = b->use_graph ? 1 : kMaxBranches;
@@ -685,7 +684,7 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
     if ((e = batch_events(b, ckks_batch_plan{B, 1, 1, 0})) != hipSuccess) break;
     for (int S = 1; S <= max_streams && e == hipSuccess; ++S) {
       if (S > 1 && S > groups + (b->n_rs ? 1 : 0)) break;
-      for (int split = 0; split <= 1 && e == hipSuccess; ++split) {
+      for (int split = 0; split <= 2 && e == hipSuccess; ++split) {
         b->plan = ckks_batch_plan{B, S, split, 0};
         if (b->use_graph && (e = batch_capture(b)) != hipSuccess) break;
         auto launch = [&]() { return b->exec ? hipGraphLaunch(b->exec, st) : batch_enqueue(b, st); };
@@ -698,6 +697,7 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
         float ms = 0.f;
         if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
         const float us = 1e3f * ms / reps;
+        b->tune_log.emplace_back(b->plan, us);
         if (top_us < 0.f || us < top_us) {
           top_us = us;
           top = b->plan;
@@ -713,6 +713,16 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
   if (ce != hipSuccess) return hip_fail(ce, "re-capturing the batch graph");
   if (best) *best = top;
   if (best_us) *best_us = top_us;
+  return CKKS_OK;
+}
+
+int ckks_batch_tune_log(const ckks_batch* b, ckks_batch_plan* plans, float* us, int cap, int* n) {
+  if (!b || !n || cap < 0 || (cap > 0 && (!plans || !us))) return fail(CKKS_EINVAL, "bad arguments");
+  *n = (int)b->tune_log.size();
+  for (int i = 0; i < std::min(cap, *n); ++i) {
+    plans[i] = b->tune_log[i].first;
+    us[i] = b->tune_log[i].second;
+  }
   return CKKS_OK;
 }
 

@@ -4,7 +4,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -99,12 +98,6 @@ struct Ctx {
   // Rescale at level L: q_{L-1}^-1 mod q_i (Shoup), i < L - 1.
   uint2* d_rescale_inv = nullptr;     // [L_max + 1][L_max]
 
-  // complementary pipelining: a side stream and fork / join events shared by
-  // the single-call entry points and batches of this context (serialised)
-  hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  mutable std::mutex side_mu;
-
   // kernel tracing (ckks_trace_begin / ckks_trace_end)
   struct Trace {
     int stage = 0;
@@ -112,14 +105,16 @@ struct Ctx {
     int count = 0;
   };
   mutable Trace trace;
-  // Record the start / stop event of a traced stage around a launch.
-  void trace_pre(int stage, hipStream_t st) const {
-    if (trace.stage == stage && trace.count < (int)trace.starts.size())
-      (void)hipEventRecord(trace.starts[trace.count], st);
-  }
-  void trace_post(int stage, hipStream_t st) const {
-    if (trace.stage == stage && trace.count < (int)trace.starts.size())
-      (void)hipEventRecord(trace.stops[trace.count++], st);
+  // The start / stop events for the next launch of a traced stage (both null
+  // when the stage is not traced or the capacity is used up).  Launchers pass
+  // them to hipExtLaunchKernel, which records them at the dispatch's own
+  // start and end.
+  void trace_take(int stage, hipEvent_t* t0, hipEvent_t* t1) const {
+    *t0 = *t1 = nullptr;
+    if (trace.stage == stage && trace.count < (int)trace.starts.size()) {
+      *t0 = trace.starts[trace.count];
+      *t1 = trace.stops[trace.count++];
+    }
   }
 
   DevTab tab() const {

@@ -46,10 +46,14 @@ constexpr int kInlineJobs = 16;
 enum KsPart : int { KS_PART_ALL = 0, KS_PART_P = 1, KS_PART_Q = 2 };
 
 // Complementary pipelining resources: a side stream and two events (fork,
-// join).  side == nullptr runs the pipeline on one stream.
+// join).  side == nullptr runs the pipeline on one stream.  The Q-row inner
+// product runs on the side stream either beside the P-row one (p_first =
+// false: both start after ModUp) or after it (p_first = true: the Q rows
+// overlap only the ModDown chain).
 struct KsSplit {
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  bool p_first = false;
 };
 
 // Jobs either inline in the kernel arguments (n <= kInlineJobs) or in a device

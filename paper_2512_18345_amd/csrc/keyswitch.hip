@@ -22,6 +22,7 @@
 // Every launch covers all jobs (grid.z) and all rows of a stage, which is
 // what gives small levels enough work-groups (the batching argument of
 // Sec. IV-A).  Rescale has its own four kernels (R1..R4).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -734,39 +735,42 @@ size_t rs_ws_words(const Ctx& c, int L) { return (2 + 2 * (size_t)L) * c.N; }
 namespace {
 constexpr int kRB = 12;  // BConv output rows per work-group (inputs re-read once per group)
 
-template <int A>
-hipError_t launch_k3(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int groups) {
-  k3_bconv_up<A, kRB><<<g, kWG, 0, st>>>(K, J, groups);
-  return hipSuccess;
-}
-template <int KP>
-hipError_t launch_k7(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int groups) {
-  k7_bconv_down<KP, kRB><<<g, kWG, 0, st>>>(K, J, groups);
-  return hipSuccess;
+// Launch of a pipeline kernel; when its stage is traced, the trace events
+// are attached to the dispatch itself.
+template <typename F, typename... A>
+void klaunch(const Ctx& c, int stage, F kern, dim3 g, hipStream_t st, A... args) {
+  hipEvent_t t0, t1;
+  c.trace_take(stage, &t0, &t1);
+  hipExtLaunchKernelGGL(kern, g, dim3(kWG), 0, st, t0, t1, 0, args...);
 }
 
 // Dispatch a small compile-time count (digit size or special-prime count, 1..16).
 template <int A>
 struct K3 {
-  static hipError_t run(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int gr) {
-    return launch_k3<A>(g, st, K, J, gr);
+  static void run(const Ctx& c, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
+                  int gr) {
+    klaunch(c, CKKS_STAGE_BCONV_UP, k3_bconv_up<A, kRB>, g, st, K, J, gr);
   }
 };
 template <int A>
 struct K7 {
-  static hipError_t run(dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J, int gr) {
-    return launch_k7<A>(g, st, K, J, gr);
+  static void run(const Ctx& c, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
+                  int gr) {
+    klaunch(c, CKKS_STAGE_BCONV_DOWN, k7_bconv_down<A, kRB>, g, st, K, J, gr);
   }
 };
 
 template <template <int> class F, int V>
-hipError_t small_dispatch(int v, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
-                          int gr) {
+hipError_t small_dispatch(int v, const Ctx& c, dim3 g, hipStream_t st, const KsConst& K,
+                          const JobArg<KsJob>& J, int gr) {
   if constexpr (V > kMaxAlpha) {
     return hipErrorInvalidValue;
   } else {
-    if (v == V) return F<V>::run(g, st, K, J, gr);
-    return small_dispatch<F, V + 1>(v, g, st, K, J, gr);
+    if (v == V) {
+      F<V>::run(c, g, st, K, J, gr);
+      return hipSuccess;
+    }
+    return small_dispatch<F, V + 1>(v, c, g, st, K, J, gr);
   }
 }
 
@@ -781,75 +785,63 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   const int down_groups = (Lmax + kRB - 1) / kRB;
   hipError_t e;
   if (with_modup) {
-    c.trace_pre(CKKS_STAGE_INTT_BLOCKS, st);
-    k1_intt_blks<L1><<<dim3(tiles, Lmax, njobs), kWG, 0, st>>>(K, jobs);
-    c.trace_post(CKKS_STAGE_INTT_BLOCKS, st);
-    c.trace_pre(CKKS_STAGE_INTT_COLS, st);
-    k2_intt_cols<L1><<<dim3(ColGeom<L1>::TILES, Lmax, njobs), kWG, 0, st>>>(K, jobs);
-    c.trace_post(CKKS_STAGE_INTT_COLS, st);
-    c.trace_pre(CKKS_STAGE_BCONV_UP, st);
-    e = small_dispatch<K3, 1>(c.alpha, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
-    c.trace_post(CKKS_STAGE_BCONV_UP, st);
+    klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1>, dim3(tiles, Lmax, njobs), st, K, jobs);
+    klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1>, dim3(ColGeom<L1>::TILES, Lmax, njobs), st, K,
+            jobs);
+    e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
     if (e != hipSuccess) return e;
-    c.trace_pre(CKKS_STAGE_NTT_COLS_UP, st);
-    k4_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), kWG, 0, st>>>(K, jobs);
-    c.trace_post(CKKS_STAGE_NTT_COLS_UP, st);
+    klaunch(c, CKKS_STAGE_NTT_COLS_UP, k4_ntt_cols<L1>, dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), st,
+            K, jobs);
   }
   // Stage 2.  With a side stream, complementary pipelining (Sec. IV-B): the
-  // inner product of the P rows runs first on st, and ModDown's P-row chain
-  // (K6..K8, ALU-heavy) overlaps with the Q-row inner product on the side
-  // stream (key streaming, HBM-heavy); K9 joins both.
-  auto k5 = [&](int part, hipStream_t s5, int rows) {
+  // inner product of the P rows runs on st and ModDown's P-row chain (K6..K8,
+  // latency-bound) follows it there, while the Q-row inner product (key
+  // streaming, HBM-heavy) runs on the side stream; K9 joins both.
+  auto k5 = [&](int stage, int part, hipStream_t s5, int rows) {
     const dim3 g5(tiles, rows, njobs);
     switch (std::max(c.beta_max(), 2)) {
-      case 2: k5s_ntt_blks_ip<L1, 2><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
-      case 3: k5s_ntt_blks_ip<L1, 3><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
-      case 4: k5s_ntt_blks_ip<L1, 4><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
-      default: k5_ntt_blks_ip<L1, false><<<g5, kWG, 0, s5>>>(K, jobs, part); break;
+      case 2: klaunch(c, stage, k5s_ntt_blks_ip<L1, 2>, g5, s5, K, jobs, part); break;
+      case 3: klaunch(c, stage, k5s_ntt_blks_ip<L1, 3>, g5, s5, K, jobs, part); break;
+      case 4: klaunch(c, stage, k5s_ntt_blks_ip<L1, 4>, g5, s5, K, jobs, part); break;
+      default: klaunch(c, stage, k5_ntt_blks_ip<L1, false>, g5, s5, K, jobs, part); break;
     }
   };
+  auto k5h = [&](int stage, int part, hipStream_t s5, int rows) {
+    klaunch(c, stage, k5_ntt_blks_ip<L1, true>, dim3(tiles, rows, njobs), s5, K, jobs, part);
+  };
   const bool split = sp.side != nullptr;
+  auto fork = [&]() -> hipError_t {
+    hipError_t fe = hipEventRecord(sp.fork, st);
+    return fe != hipSuccess ? fe : hipStreamWaitEvent(sp.side, sp.fork, 0);
+  };
+  auto part_q = [&]() {
+    if (with_modup) k5(CKKS_STAGE_NTT_IP, KS_PART_Q, sp.side, Lmax);
+    if (with_hoist) k5h(CKKS_STAGE_NTT_IP, KS_PART_Q, sp.side, Lmax);
+  };
   if (split) {
-    if ((e = hipEventRecord(sp.fork, st)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(sp.side, sp.fork, 0)) != hipSuccess) return e;
-  }
-  if (with_modup) {
-    if (split) {
-      c.trace_pre(CKKS_STAGE_NTT_IP, sp.side);
-      k5(KS_PART_Q, sp.side, Lmax);
-      c.trace_post(CKKS_STAGE_NTT_IP, sp.side);
-      c.trace_pre(CKKS_STAGE_NTT_IP_P, st);
-      k5(KS_PART_P, st, c.k);
-      c.trace_post(CKKS_STAGE_NTT_IP_P, st);
-    } else {
-      c.trace_pre(CKKS_STAGE_NTT_IP, st);
-      k5(KS_PART_ALL, st, Rmax);
-      c.trace_post(CKKS_STAGE_NTT_IP, st);
+    if (!sp.p_first) {
+      if ((e = fork()) != hipSuccess) return e;
+      part_q();
     }
-  }
-  if (with_hoist) {
-    if (split) {
-      k5_ntt_blks_ip<L1, true><<<dim3(tiles, Lmax, njobs), kWG, 0, sp.side>>>(K, jobs, KS_PART_Q);
-      k5_ntt_blks_ip<L1, true><<<dim3(tiles, c.k, njobs), kWG, 0, st>>>(K, jobs, KS_PART_P);
-    } else {
-      k5_ntt_blks_ip<L1, true><<<dim3(tiles, Rmax, njobs), kWG, 0, st>>>(K, jobs, KS_PART_ALL);
+    if (with_modup) k5(CKKS_STAGE_NTT_IP_P, KS_PART_P, st, c.k);
+    if (with_hoist) k5h(CKKS_STAGE_NTT_IP_P, KS_PART_P, st, c.k);
+    if (sp.p_first) {
+      if ((e = fork()) != hipSuccess) return e;
+      part_q();
     }
+  } else {
+    if (with_modup) k5(CKKS_STAGE_NTT_IP, KS_PART_ALL, st, Rmax);
+    if (with_hoist) k5h(CKKS_STAGE_NTT_IP, KS_PART_ALL, st, Rmax);
   }
   if (split && (e = hipEventRecord(sp.join, sp.side)) != hipSuccess) return e;
-  c.trace_pre(CKKS_STAGE_INTT_COLS_P, st);
-  k6_intt_cols_p<L1><<<dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), kWG, 0, st>>>(K, jobs);
-  c.trace_post(CKKS_STAGE_INTT_COLS_P, st);
-  c.trace_pre(CKKS_STAGE_BCONV_DOWN, st);
-  e = small_dispatch<K7, 1>(c.k, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
-  c.trace_post(CKKS_STAGE_BCONV_DOWN, st);
+  klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1>, dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), st,
+          K, jobs);
+  e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
   if (e != hipSuccess) return e;
-  c.trace_pre(CKKS_STAGE_NTT_COLS_DOWN, st);
-  k8_ntt_cols_w<L1><<<dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
-  c.trace_post(CKKS_STAGE_NTT_COLS_DOWN, st);
+  klaunch(c, CKKS_STAGE_NTT_COLS_DOWN, k8_ntt_cols_w<L1>, dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), st,
+          K, jobs);
   if (split && (e = hipStreamWaitEvent(st, sp.join, 0)) != hipSuccess) return e;
-  c.trace_pre(CKKS_STAGE_NTT_COMBINE, st);
-  k9_ntt_blks_combine<L1><<<dim3(tiles, 2 * Lmax, njobs), kWG, 0, st>>>(K, jobs);
-  c.trace_post(CKKS_STAGE_NTT_COMBINE, st);
+  klaunch(c, CKKS_STAGE_NTT_COMBINE, k9_ntt_blks_combine<L1>, dim3(tiles, 2 * Lmax, njobs), st, K, jobs);
   return hipGetLastError();
 }
 
@@ -860,9 +852,8 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
   r1_intt_blks<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
   r2_intt_cols<L1><<<dim3(ColGeom<L1>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
   r3_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
-  c.trace_pre(CKKS_STAGE_RESCALE_NTT, st);
-  r4_ntt_blks_combine<L1><<<dim3(tiles, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
-  c.trace_post(CKKS_STAGE_RESCALE_NTT, st);
+  klaunch(c, CKKS_STAGE_RESCALE_NTT, r4_ntt_blks_combine<L1>, dim3(tiles, 2 * (Lmax - 1), njobs), st, K,
+          jobs);
   return hipGetLastError();
 }
 }  // namespace

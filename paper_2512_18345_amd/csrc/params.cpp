@@ -242,12 +242,6 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
   if (!(err = upload(&c.d_moddown_T, dT, code)).empty()) return err;
   if (!(err = upload(&c.d_pinv, pinv, code)).empty()) return err;
   if (!(err = upload(&c.d_rescale_inv, rinv, code)).empty()) return err;
-  if (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c.fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c.join_ev, hipEventDisableTiming) != hipSuccess) {
-    *code = CKKS_EHIP;
-    return "creating the side stream / events failed";
-  }
   *code = CKKS_OK;
   return "";
 }
@@ -257,9 +251,6 @@ void free_tables(Ctx& c) {
                   c.d_moddown_scale, c.d_moddown_T, c.d_pinv, c.d_rescale_inv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  if (c.side) (void)hipStreamDestroy(c.side);
-  if (c.fork_ev) (void)hipEventDestroy(c.fork_ev);
-  if (c.join_ev) (void)hipEventDestroy(c.join_ev);
 }
 
 }  // namespace ckks

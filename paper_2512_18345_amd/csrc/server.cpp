@@ -116,8 +116,6 @@ struct ckks_server {
   void* d_arena = nullptr;
   Arena arena;
   hipStream_t streams[kStreams] = {};
-  hipStream_t sides[kStreams] = {};  // complementary-pipelining partner of each stream
-  hipEvent_t forks[kStreams] = {}, joins[kStreams] = {};
   int next_stream = 0;
   // per ring slot: device and pinned host job tables of max_slots entries
   KsJob* d_ks[kRing] = {};
@@ -216,8 +214,7 @@ struct ckks_server {
     if (e == hipSuccess && nks) {
       JobArg<KsJob> ka{};
       ka.table = d_ks[ring];
-      e = ks_launch(c, ka, nks, Lks, true, false, st,
-                    KsSplit{sides[f.stream], forks[f.stream], joins[f.stream]});
+      e = ks_launch(c, ka, nks, Lks, true, false, st);
     }
     if (e == hipSuccess && nrs) {
       JobArg<RsJob> ra{};
@@ -275,12 +272,8 @@ void server_free(ckks_server* s) {
     if (s->h_rs[i]) (void)hipHostFree(s->h_rs[i]);
     if (s->events[i]) (void)hipEventDestroy(s->events[i]);
   }
-  for (int i = 0; i < kStreams; ++i) {
-    if (s->streams[i]) (void)hipStreamDestroy(s->streams[i]);
-    if (s->sides[i]) (void)hipStreamDestroy(s->sides[i]);
-    if (s->forks[i]) (void)hipEventDestroy(s->forks[i]);
-    if (s->joins[i]) (void)hipEventDestroy(s->joins[i]);
-  }
+  for (hipStream_t st : s->streams)
+    if (st) (void)hipStreamDestroy(st);
   if (s->d_arena) (void)hipFree(s->d_arena);
   delete s;
 }
@@ -321,10 +314,7 @@ int ckks_server_create(const ckks_ctx* const* ctxs, int nctx, size_t hbm_budget,
   }
   bool ok = hipMalloc(&s->d_arena, hbm_budget) == hipSuccess;
   for (int i = 0; ok && i < kStreams; ++i)
-    ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess &&
-         hipStreamCreateWithFlags(&s->sides[i], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&s->forks[i], hipEventDisableTiming) == hipSuccess &&
-         hipEventCreateWithFlags(&s->joins[i], hipEventDisableTiming) == hipSuccess;
+    ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; ok && i < kRing; ++i) {
     ok = hipMalloc(&s->d_ks[i], sizeof(KsJob) * max_slots) == hipSuccess &&
          hipMalloc(&s->d_rs[i], sizeof(RsJob) * max_slots) == hipSuccess &&
@@ -434,10 +424,8 @@ int ckks_server_destroy(ckks_server* s) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(s->device);
-  for (int i = 0; i < kStreams; ++i) {
-    if (s->streams[i]) (void)hipStreamSynchronize(s->streams[i]);
-    if (s->sides[i]) (void)hipStreamSynchronize(s->sides[i]);
-  }
+  for (hipStream_t st : s->streams)
+    if (st) (void)hipStreamSynchronize(st);
   server_free(s);
   (void)hipSetDevice(prev);
   return CKKS_OK;

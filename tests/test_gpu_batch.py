@@ -130,6 +130,8 @@ def _check_plans(use_graph, plans):
         print(f"tune graph={use_graph}", flush=True)
         plan, us = P.ckks_batch_tune(b, reps=1)
         assert us > 0 and plan == P.ckks_batch_get_plan(b)
+        log = P.ckks_batch_tune_log(b)
+        assert len(log) >= 3 and min(t for _, t in log) == us and (plan, us) in log
         for j in jobs:
             j["out"].fill_(-1)
         P.ckks_batch_launch(b)
@@ -144,12 +146,12 @@ def _check_plans(use_graph, plans):
 def test_graph_plans_give_the_single_call_results():
     """Launch groups and the split inner product change only the schedule:
     each one-branch plan of a graph batch reproduces the single calls bitwise."""
-    _check_plans(True, [(0, 1, 0), (3, 1, 1), (2, 1, 0), (8, 1, 1), (1, 1, 1)])
+    _check_plans(True, [(0, 1, 0), (3, 1, 1), (2, 1, 0), (8, 1, 2), (1, 1, 1), (4, 1, 2)])
 
 
 def test_eager_plans_give_the_single_call_results():
     """Eager batches may also spread launch groups over concurrent branches."""
-    _check_plans(False, [(0, 1, 0), (0, 2, 1), (1, 4, 1), (2, 3, 0), (3, 2, 1), (8, 1, 1)])
+    _check_plans(False, [(0, 1, 0), (0, 2, 1), (1, 4, 2), (2, 3, 0), (3, 2, 1), (8, 1, 2)])
 
 
 def test_graph_batch_rejects_several_branches():
