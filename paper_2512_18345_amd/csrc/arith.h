@@ -71,4 +71,26 @@ __device__ __forceinline__ T ldc(const T* p) {
   return v;
 }
 
+
+// Global-memory accesses through the global address space.  Data pointers
+// that come from job tables are generic (flat) pointers, which the compiler
+// must assume may alias LDS: each flat load would then wait for the LDS
+// stores before it.  Accessing them as global memory lets loads be issued
+// back to back.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld4(const uint32_t* p) {
+  const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4(uint32_t* p, uint4 v) {
+  const u32x4 w = {v.x, v.y, v.z, v.w};
+  *(__attribute__((address_space(1))) u32x4*)p = w;
+}
+__device__ __forceinline__ uint32_t ld1(const uint32_t* p) {
+  return *(const __attribute__((address_space(1))) uint32_t*)p;
+}
+__device__ __forceinline__ void st1(uint32_t* p, uint32_t v) {
+  *(__attribute__((address_space(1))) uint32_t*)p = v;
+}
+
 }  // namespace ckks

@@ -24,12 +24,14 @@ __global__ __launch_bounds__(kWG) void k_ntt_cols(DevTab T, RowMap rm, const uin
   const int r = blockIdx.y;
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, T.col_tw(pi), ColGeom<LOGN1>::N1);
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
   load_cols<LOGN1>(s, src + r * N, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, T.col_tw(pi), q, q2);
+  col_stages<LOGN1, false>(s, stw, q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, dst + r * N, col0);
 }
@@ -42,6 +44,8 @@ __global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uin
   const int r = blockIdx.y;
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
+  __shared__ uint2 stw[256];
+  stage_tw(stw, T.blk_tw(pi), 256);
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -50,16 +54,16 @@ __global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uin
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = blk_elem(k);
-    lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(in + e),
+    lds_blk4_store(s, e, twist4(ld4(in + e),
                                 T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, T.blk_tw(pi), q, q2);
+  blk_stages<false>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = blk_elem(k);
-    *reinterpret_cast<uint4*>(out + e) = canon4(lds_blk4(s, e), q, q2);
+    st4(out + e, canon4(lds_blk4(s, e), q, q2));
   }
 }
 
@@ -71,6 +75,8 @@ __global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const ui
   const int r = blockIdx.y;
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
+  __shared__ uint2 stw[256];
+  stage_tw(stw, T.blk_itw(pi), 256);
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -79,16 +85,15 @@ __global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const ui
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = blk_elem(k);
-    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
+    lds_blk4_store(s, e, ld4(in + e));
   }
   __syncthreads();
-  blk_stages<true>(s, T.blk_itw(pi), q, q2);
+  blk_stages<true>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = blk_elem(k);
-    *reinterpret_cast<uint4*>(out + e) =
-        twist4(lds_blk4(s, e), T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q);
+    st4(out + e, twist4(lds_blk4(s, e), T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q));
   }
 }
 
@@ -104,6 +109,8 @@ __global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const ui
   const int r = blockIdx.y;
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, T.col_itw(pi), ColGeom<LOGN1>::N1);
   const size_t N = (size_t)1 << T.logN;
   const ModC mc = T.mod[pi];
   const uint32_t q = mc.q, q2 = 2 * q;
@@ -111,7 +118,7 @@ __global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const ui
   const int col0 = blockIdx.x * C;
   load_cols<LOGN1>(s, src + r * N, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, T.col_itw(pi), q, q2);
+  col_stages<LOGN1, true>(s, stw, q, q2);
   __syncthreads();
   uint32_t* row = dst + r * N;
 #pragma unroll
@@ -123,7 +130,7 @@ __global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const ui
     v.y = csub(mul_shoup(v.y, sc.x, sc.y, q), q);
     v.z = csub(mul_shoup(v.z, sc.x, sc.y, q), q);
     v.w = csub(mul_shoup(v.w, sc.x, sc.y, q), q);
-    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) = v;
+    st4(row + pos * 256 + col0 + c, v);
   }
 }
 

@@ -88,21 +88,37 @@ __device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const ModC& m
   return reduce64((uint64_t)a * b, m.q, m.mu_hi, m.mu_lo);
 }
 
-// Four consecutive eval-domain words n..n+3 of row r of the polynomial a job
-// key-switches: d (PLAIN), c1 c1' (HMULT), sigma(c1) (HROT / HOIST).
-__device__ __forceinline__ uint4 load_d4(const KsJob& J, int r, uint32_t n, size_t N, int logN,
-                                         const ModC& m) {
-  if (J.kind == KS_PLAIN) return *reinterpret_cast<const uint4*>(J.a + (size_t)r * N + n);
+// The four quads (words base + blk_elem(kk) .. +3) of row r of the polynomial
+// a job key-switches: d (PLAIN), c1 c1' (HMULT), sigma(c1) (HROT / HOIST).
+// Every load of a quad is issued before any of them is used.
+__device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, size_t N, int logN,
+                                         const ModC& m, uint4 d[4]) {
+  if (J.kind == KS_PLAIN) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) d[kk] = ld4(J.a + (size_t)r * N + base + blk_elem(kk));
+    return;
+  }
   const size_t row1 = (size_t)(J.L + r) * N;
   if (J.kind == KS_HMULT) {
-    const uint4 x = *reinterpret_cast<const uint4*>(J.a + row1 + n);
-    const uint4 y = *reinterpret_cast<const uint4*>(J.b + row1 + n);
-    return make_uint4(mulmod(x.x, y.x, m), mulmod(x.y, y.y, m), mulmod(x.z, y.z, m),
-                      mulmod(x.w, y.w, m));
+    uint4 x[4], y[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      x[kk] = ld4(J.a + row1 + base + blk_elem(kk));
+      y[kk] = ld4(J.b + row1 + base + blk_elem(kk));
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      d[kk] = make_uint4(mulmod(x[kk].x, y[kk].x, m), mulmod(x[kk].y, y[kk].y, m),
+                         mulmod(x[kk].z, y[kk].z, m), mulmod(x[kk].w, y[kk].w, m));
+    return;
   }
   const uint32_t* src = J.a + row1;
-  return make_uint4(src[auto_src(n, J.gal, logN)], src[auto_src(n + 1, J.gal, logN)],
-                    src[auto_src(n + 2, J.gal, logN)], src[auto_src(n + 3, J.gal, logN)]);
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const uint32_t n = base + blk_elem(kk);
+    d[kk] = make_uint4(ld1(src + auto_src(n, J.gal, logN)), ld1(src + auto_src(n + 1, J.gal, logN)),
+                       ld1(src + auto_src(n + 2, J.gal, logN)), ld1(src + auto_src(n + 3, J.gal, logN)));
+  }
 }
 
 // ============================================================================
@@ -119,26 +135,29 @@ __global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA)
   const size_t N = (size_t)1 << logN;
   const ModC m = ldc(K.T.mod + r);
   const uint32_t q = m.q, q2 = 2 * q;
+  __shared__ uint2 stw[256];
+  stage_tw(stw, K.T.blk_itw(r), 256);
   const int blk0 = blockIdx.x * 16;
   const uint32_t base = blk0 * 256;
   const KsView V = ks_view(J, K, N);
   uint32_t* de = V.de + (size_t)r * N + base;
+  // all loads first: a store to de could alias the next quad's source
+  uint4 d[4];
+  load_d16(J, r, base, N, logN, m, d);
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    const uint4 d = load_d4(J, r, base + e, N, logN, m);
-    lds_blk4_store(s, e, d);
-    if (J.kind != KS_PLAIN) *reinterpret_cast<uint4*>(de + e) = d;
+    lds_blk4_store(s, e, d[kk]);
+    if (J.kind != KS_PLAIN) st4(de + e, d[kk]);
   }
   __syncthreads();
-  blk_stages<true>(s, K.T.blk_itw(r), q, q2);
+  blk_stages<true>(s, stw, q, q2);
   __syncthreads();
   uint32_t* y = V.y + (size_t)r * N + base;
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    *reinterpret_cast<uint4*>(y + e) =
-        twist4(lds_blk4(s, e), K.T.blk_itwist(r, blk0 + (e >> 8)), e & 255, q);
+    st4(y + e, twist4(lds_blk4(s, e), K.T.blk_itwist(r, blk0 + (e >> 8)), e & 255, q));
   }
 }
 
@@ -151,12 +170,14 @@ __global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA)
   constexpr int C = ColGeom<LOGN1>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + r).q, q2 = 2 * q;
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, K.T.col_itw(r), ColGeom<LOGN1>::N1);
   const uint2 sc = ldc(K.modup_scale + (size_t)J.L * K.T.L_max + r);
   const int col0 = blockIdx.x * C;
   uint32_t* row = ks_view(J, K, N).y + (size_t)r * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, K.T.col_itw(r), q, q2);
+  col_stages<LOGN1, true>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
@@ -167,7 +188,7 @@ __global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA)
     v.y = csub(mul_shoup(v.y, sc.x, sc.y, q), q);
     v.z = csub(mul_shoup(v.z, sc.x, sc.y, q), q);
     v.w = csub(mul_shoup(v.w, sc.x, sc.y, q), q);
-    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) = v;
+    st4(row + pos * 256 + col0 + c, v);
   }
 }
 
@@ -186,7 +207,7 @@ __global__ __launch_bounds__(kWG) void k3_bconv_up(KsConst K, JobArg<KsJob> JA, 
   const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
   uint32_t x[ALPHA];
 #pragma unroll
-  for (int i = 0; i < ALPHA; ++i) x[i] = V.y[(size_t)min(lo + i, V.L - 1) * N + n];
+  for (int i = 0; i < ALPHA; ++i) x[i] = ld1(V.y + (size_t)min(lo + i, V.L - 1) * N + n);
   const uint32_t* Tt = K.modup_T + ldc(K.modup_T_off + (size_t)V.L * K.beta_max + j);
   const int r1 = min(g * RB + RB, V.R);
   for (int r = g * RB; r < r1; ++r) {
@@ -196,7 +217,7 @@ __global__ __launch_bounds__(kWG) void k3_bconv_up(KsConst K, JobArg<KsJob> JA, 
     uint64_t acc = 0;
 #pragma unroll
     for (int i = 0; i < ALPHA; ++i) acc += (uint64_t)x[i] * ldc(t + i);
-    V.z[((size_t)j * V.R + r) * N + n] = reduce64(acc, m.q, m.mu_hi, m.mu_lo);
+    st1(V.z + ((size_t)j * V.R + r) * N + n, reduce64(acc, m.q, m.mu_hi, m.mu_lo));
   }
 }
 
@@ -213,12 +234,14 @@ __global__ __launch_bounds__(kWG) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) 
   if (r >= lo && r < hi) return;
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, K.T.col_tw(pi), ColGeom<LOGN1>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
   const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
   uint32_t* row = V.z + (size_t)gr * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, K.T.col_tw(pi), q, q2);
+  col_stages<LOGN1, false>(s, stw, q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, row, col0);
 }
@@ -238,6 +261,9 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
   if (r >= V.R || (part == KS_PART_Q && r >= V.L) || (J.kind == KS_HOIST) != HOIST) return;
   __shared__ __align__(16) uint32_t s[kLds];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
+  __shared__ uint2 stw[256], stwi[256];
+  stage_tw(stw, K.T.blk_tw(pi), 256);
+  if (r >= V.L) stage_tw(stwi, K.T.blk_itw(pi), 256);
   const ModC m = ldc(K.T.mod + pi);
   const uint32_t q = m.q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -256,25 +282,25 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const uint32_t n = base + blk_elem(kk);
-        v[kk] = make_uint4(Mrow[auto_src(n, J.gal, logN)], Mrow[auto_src(n + 1, J.gal, logN)],
-                           Mrow[auto_src(n + 2, J.gal, logN)], Mrow[auto_src(n + 3, J.gal, logN)]);
+        v[kk] = make_uint4(ld1(Mrow + auto_src(n, J.gal, logN)), ld1(Mrow + auto_src(n + 1, J.gal, logN)),
+                           ld1(Mrow + auto_src(n + 2, J.gal, logN)), ld1(Mrow + auto_src(n + 3, J.gal, logN)));
       }
     } else if (r >= lo && r < hi) {
       // digit rows are the switched polynomial itself (kept by K1 unless it is the input)
       const uint32_t* drow = (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) v[kk] = *reinterpret_cast<const uint4*>(drow + blk_elem(kk));
+      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(drow + blk_elem(kk));
     } else {
       const uint32_t* zrow = V.z + ((size_t)j * V.R + r) * N + base;
       __syncthreads();  // the previous digit's tile has been read
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int e = blk_elem(kk);
-        lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(zrow + e),
+        lds_blk4_store(s, e, twist4(ld4(zrow + e),
                                     K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
       }
       __syncthreads();
-      blk_stages<false>(s, K.T.blk_tw(pi), q, q2);
+      blk_stages<false>(s, stw, q, q2);
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) v[kk] = canon4(lds_blk4(s, blk_elem(kk)), q, q2);
@@ -283,7 +309,7 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
     const uint32_t* k1 = k0 + KR * N;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const uint4 e0 = *reinterpret_cast<const uint4*>(k0 + blk_elem(kk));
+      const uint4 e0 = ld4(k0 + blk_elem(kk));
       a0[4 * kk + 0] += (uint64_t)v[kk].x * e0.x;
       a0[4 * kk + 1] += (uint64_t)v[kk].y * e0.y;
       a0[4 * kk + 2] += (uint64_t)v[kk].z * e0.z;
@@ -291,7 +317,7 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const uint4 e1 = *reinterpret_cast<const uint4*>(k1 + blk_elem(kk));
+      const uint4 e1 = ld4(k1 + blk_elem(kk));
       a1[4 * kk + 0] += (uint64_t)v[kk].x * e1.x;
       a1[4 * kk + 1] += (uint64_t)v[kk].y * e1.y;
       a1[4 * kk + 2] += (uint64_t)v[kk].z * e1.z;
@@ -312,8 +338,8 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int e = blk_elem(kk);
-      *reinterpret_cast<uint4*>(acc0 + e) = make_uint4(r0[4 * kk], r0[4 * kk + 1], r0[4 * kk + 2], r0[4 * kk + 3]);
-      *reinterpret_cast<uint4*>(acc1 + e) = make_uint4(r1[4 * kk], r1[4 * kk + 1], r1[4 * kk + 2], r1[4 * kk + 3]);
+      st4(acc0 + e, make_uint4(r0[4 * kk], r0[4 * kk + 1], r0[4 * kk + 2], r0[4 * kk + 3]));
+      st4(acc1 + e, make_uint4(r1[4 * kk], r1[4 * kk + 1], r1[4 * kk + 2], r1[4 * kk + 3]));
     }
     return;
   }
@@ -327,13 +353,12 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
       lds_blk4_store(s, blk_elem(kk), make_uint4(rr[4 * kk], rr[4 * kk + 1], rr[4 * kk + 2], rr[4 * kk + 3]));
     }
     __syncthreads();
-    blk_stages<true>(s, K.T.blk_itw(pi), q, q2);
+    blk_stages<true>(s, stwi, q, q2);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int e = blk_elem(kk);
-      *reinterpret_cast<uint4*>(dst + e) =
-          twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q);
+      st4(dst + e, twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q));
     }
   }
 }
@@ -369,18 +394,31 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int e = blk_elem(kk);
-        lds_blk4_store(slot, e, *reinterpret_cast<const uint4*>(drow + e));
+        lds_blk4_store(slot, e, ld4(drow + e));
       }
     } else {
       const uint32_t* zrow = V.z + ((size_t)j * V.R + r) * N + base;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int e = blk_elem(kk);
-        lds_blk4_store(slot, e, twist4(*reinterpret_cast<const uint4*>(zrow + e),
+        lds_blk4_store(slot, e, twist4(ld4(zrow + e),
                                        K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
       }
     }
   }
+  // The key words of the first KPF quads are requested now, after the digit
+  // loads, so that their latency overlaps the transforms below.
+  constexpr int KPF = 2;
+  uint4 kpre0[KPF][NB], kpre1[KPF][NB];
+#pragma unroll
+  for (int kk = 0; kk < KPF; ++kk)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j >= V.beta) break;
+      const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pi) * N + base + blk_elem(kk);
+      kpre0[kk][j] = ld4(k0);
+      kpre1[kk][j] = ld4(k0 + KR * N);
+    }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -402,9 +440,15 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
     for (int j = 0; j < NB; ++j) {
       if (j >= V.beta) break;
       const uint4 v = canon4(lds_blk4(s + j * kLds, e), q, q2);
-      const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pi) * N + base + e;
-      const uint4 e0 = *reinterpret_cast<const uint4*>(k0);
-      const uint4 e1 = *reinterpret_cast<const uint4*>(k0 + KR * N);
+      uint4 e0, e1;
+      if (kk < KPF) {
+        e0 = kpre0[kk][j];
+        e1 = kpre1[kk][j];
+      } else {
+        const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pi) * N + base + e;
+        e0 = ld4(k0);
+        e1 = ld4(k0 + KR * N);
+      }
       a0[0] += (uint64_t)v.x * e0.x;
       a0[1] += (uint64_t)v.y * e0.y;
       a0[2] += (uint64_t)v.z * e0.z;
@@ -425,12 +469,13 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int e = blk_elem(kk);
-      *reinterpret_cast<uint4*>(acc0 + e) = res0[kk];
-      *reinterpret_cast<uint4*>(acc1 + e) = res1[kk];
+      st4(acc0 + e, res0[kk]);
+      st4(acc1 + e, res1[kk]);
     }
     return;
   }
   // P rows: the INTT block pass of ModDown on both components (slots 0 and 1)
+  // (twiddles from global memory: 2 KB more LDS would cost a resident work-group)
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -445,8 +490,8 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
     const uint2* tb = K.T.blk_itwist(pi, blk0 + (e >> 8));
-    *reinterpret_cast<uint4*>(acc0 + e) = twist4(lds_blk4(s, e), tb, e & 255, q);
-    *reinterpret_cast<uint4*>(acc1 + e) = twist4(lds_blk4(s + kLds, e), tb, e & 255, q);
+    st4(acc0 + e, twist4(lds_blk4(s, e), tb, e & 255, q));
+    st4(acc1 + e, twist4(lds_blk4(s + kLds, e), tb, e & 255, q));
   }
 }
 
@@ -464,12 +509,14 @@ __global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> J
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   constexpr int C = ColGeom<LOGN1>::C;
   const int pi = K.T.L_max + mm;
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
   const uint2 sc = ldc(K.moddown_scale + mm);
   const int col0 = blockIdx.x * C;
   load_cols<LOGN1>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, K.T.col_itw(pi), q, q2);
+  col_stages<LOGN1, true>(s, stw, q, q2);
   __syncthreads();
   uint32_t* row = V.x + ((size_t)c * K.k + mm) * N;
 #pragma unroll
@@ -481,7 +528,7 @@ __global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> J
     v.y = csub(mul_shoup(v.y, sc.x, sc.y, q), q);
     v.z = csub(mul_shoup(v.z, sc.x, sc.y, q), q);
     v.w = csub(mul_shoup(v.w, sc.x, sc.y, q), q);
-    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + cc) = v;
+    st4(row + pos * 256 + col0 + cc, v);
   }
 }
 
@@ -496,7 +543,7 @@ __global__ __launch_bounds__(kWG) void k7_bconv_down(KsConst K, JobArg<KsJob> JA
   const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
   uint32_t x[KP];
 #pragma unroll
-  for (int mm = 0; mm < KP; ++mm) x[mm] = V.x[((size_t)c * KP + mm) * N + n];
+  for (int mm = 0; mm < KP; ++mm) x[mm] = ld1(V.x + ((size_t)c * KP + mm) * N + n);
   const int r1 = min(g * RB + RB, V.L);
   for (int i = g * RB; i < r1; ++i) {
     const ModC m = ldc(K.T.mod + i);
@@ -504,7 +551,7 @@ __global__ __launch_bounds__(kWG) void k7_bconv_down(KsConst K, JobArg<KsJob> JA
     uint64_t acc = 0;
 #pragma unroll
     for (int mm = 0; mm < KP; ++mm) acc += (uint64_t)x[mm] * ldc(t + mm);
-    V.w[((size_t)c * V.L + i) * N + n] = reduce64(acc, m.q, m.mu_hi, m.mu_lo);
+    st1(V.w + ((size_t)c * V.L + i) * N + n, reduce64(acc, m.q, m.mu_hi, m.mu_lo));
   }
 }
 
@@ -516,13 +563,15 @@ __global__ __launch_bounds__(kWG) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA
   const int gr = blockIdx.y;
   if (gr >= 2 * V.L) return;
   const int i = gr % V.L;
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1>::N1);
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
   const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
   uint32_t* row = V.w + (size_t)gr * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, K.T.col_tw(i), q, q2);
+  col_stages<LOGN1, false>(s, stw, q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, row, col0);
 }
@@ -537,6 +586,8 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
   const int gr = blockIdx.y;
   if (gr >= 2 * V.L) return;
   const int c = gr / V.L, i = gr % V.L;
+  __shared__ uint2 stw[256];
+  stage_tw(stw, K.T.blk_tw(i), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const ModC m = ldc(K.T.mod + i);
   const uint32_t q = m.q, q2 = 2 * q;
@@ -546,37 +597,57 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(wrow + e),
+    lds_blk4_store(s, e, twist4(ld4(wrow + e),
                                 K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, K.T.blk_tw(i), q, q2);
+  blk_stages<false>(s, stw, q, q2);
   __syncthreads();
   const uint2 pv = ldc(K.pinv + i);
   const uint32_t* accr = V.acc + ((size_t)c * V.R + i) * N + base;
   uint32_t* out = J.out + ((size_t)c * V.L + i) * N + base;
   const size_t L = V.L;
+  const bool hmult = J.kind == KS_HMULT;
+  const bool rot = (J.kind == KS_HROT || J.kind == KS_HOIST) && c == 0;
+  // all loads first (a store to out could alias a later load), then the combine
+  uint4 av[4], x0[4], y0[4], x1[4], y1[4];
+  uint32_t g[4][4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    const uint32_t n = base + e;
+    av[kk] = ld4(accr + e);
+    if (hmult) {
+      x0[kk] = ld4(J.a + i * N + n);
+      y0[kk] = ld4(J.b + i * N + n);
+      if (c == 1) {
+        x1[kk] = ld4(J.a + (L + i) * N + n);
+        y1[kk] = ld4(J.b + (L + i) * N + n);
+      }
+    } else if (rot) {
+      const uint32_t* c0 = J.a + i * N;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) g[kk][t] = ld1(c0 + auto_src(n + t, J.gal, logN));
+    }
+  }
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
     const uint4 w = canon4(lds_blk4(s, e), q, q2);
-    const uint4 a = *reinterpret_cast<const uint4*>(accr + e);
+    const uint4 a = av[kk];
     uint32_t o[4] = {a.x + q - w.x, a.y + q - w.y, a.z + q - w.z, a.w + q - w.w};
 #pragma unroll
     for (int t = 0; t < 4; ++t) o[t] = csub(mul_shoup(o[t], pv.x, pv.y, q), q);
-    const uint32_t n = base + e;
-    if (J.kind == KS_HMULT) {
+    if (hmult) {
       // d0 = c0 c0' (c = 0) or d1 = c0 c1' + c1 c0' (c = 1), formed here from the inputs
-      const uint4 x0 = *reinterpret_cast<const uint4*>(J.a + i * N + n);
-      const uint4 y0 = *reinterpret_cast<const uint4*>(J.b + i * N + n);
-      const uint32_t xa[4] = {x0.x, x0.y, x0.z, x0.w}, ya[4] = {y0.x, y0.y, y0.z, y0.w};
+      const uint32_t xa[4] = {x0[kk].x, x0[kk].y, x0[kk].z, x0[kk].w};
+      const uint32_t ya[4] = {y0[kk].x, y0[kk].y, y0[kk].z, y0[kk].w};
       if (c == 0) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) o[t] = csub(o[t] + mulmod(xa[t], ya[t], m), q);
       } else {
-        const uint4 x1 = *reinterpret_cast<const uint4*>(J.a + (L + i) * N + n);
-        const uint4 y1 = *reinterpret_cast<const uint4*>(J.b + (L + i) * N + n);
-        const uint32_t xb[4] = {x1.x, x1.y, x1.z, x1.w}, yb[4] = {y1.x, y1.y, y1.z, y1.w};
+        const uint32_t xb[4] = {x1[kk].x, x1[kk].y, x1[kk].z, x1[kk].w};
+        const uint32_t yb[4] = {y1[kk].x, y1[kk].y, y1[kk].z, y1[kk].w};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const uint32_t d1 =
@@ -584,12 +655,11 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
           o[t] = csub(o[t] + d1, q);
         }
       }
-    } else if ((J.kind == KS_HROT || J.kind == KS_HOIST) && c == 0) {
-      const uint32_t* c0 = J.a + i * N;
+    } else if (rot) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) o[t] = csub(o[t] + c0[auto_src(n + t, J.gal, logN)], q);
+      for (int t = 0; t < 4; ++t) o[t] = csub(o[t] + g[kk][t], q);
     }
-    *reinterpret_cast<uint4*>(out + e) = make_uint4(o[0], o[1], o[2], o[3]);
+    st4(out + e, make_uint4(o[0], o[1], o[2], o[3]));
   }
 }
 
@@ -601,6 +671,8 @@ template <int LOGN1>
 __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, L = J.L, pi = L - 1;
+  __shared__ uint2 stw[256];
+  stage_tw(stw, K.T.blk_itw(pi), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
@@ -610,16 +682,15 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    lds_blk4_store(s, e, *reinterpret_cast<const uint4*>(in + e));
+    lds_blk4_store(s, e, ld4(in + e));
   }
   __syncthreads();
-  blk_stages<true>(s, K.T.blk_itw(pi), q, q2);
+  blk_stages<true>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    *reinterpret_cast<uint4*>(t + e) =
-        twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q);
+    st4(t + e, twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q));
   }
 }
 
@@ -627,6 +698,8 @@ template <int LOGN1>
 __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, pi = J.L - 1;
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1>::N1);
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   constexpr int C = ColGeom<LOGN1>::C;
   const size_t N = (size_t)1 << K.T.logN;
@@ -636,7 +709,7 @@ __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA)
   uint32_t* row = J.ws + (size_t)c * N;
   load_cols<LOGN1>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, K.T.col_itw(pi), q, q2);
+  col_stages<LOGN1, true>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
@@ -647,7 +720,7 @@ __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA)
     v.y = csub(mul_shoup(v.y, m.ninv, m.ninv_s, q), q);
     v.z = csub(mul_shoup(v.z, m.ninv, m.ninv_s, q), q);
     v.w = csub(mul_shoup(v.w, m.ninv, m.ninv_s, q), q);
-    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + cc) = v;
+    st4(row + pos * 256 + col0 + cc, v);
   }
 }
 
@@ -659,6 +732,8 @@ __global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) 
   const int gr = blockIdx.y;
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
+  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
+  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1>::N1);
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
   constexpr int C = ColGeom<LOGN1>::C;
   const size_t N = (size_t)1 << K.T.logN;
@@ -670,7 +745,7 @@ __global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) 
   for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
-    uint4 v = *reinterpret_cast<const uint4*>(t + pos * 256 + col0 + cc);
+    uint4 v = ld4(t + pos * 256 + col0 + cc);
     v.x = reduce32(v.x, q, m.mu32);
     v.y = reduce32(v.y, q, m.mu32);
     v.z = reduce32(v.z, q, m.mu32);
@@ -678,7 +753,7 @@ __global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) 
     *reinterpret_cast<uint4*>(s + lidx_col(pos, cc, C)) = v;
   }
   __syncthreads();
-  col_stages<LOGN1, false>(s, K.T.col_tw(i), q, q2);
+  col_stages<LOGN1, false>(s, stw, q, q2);
   __syncthreads();
   store_cols<LOGN1>(s, J.ws + (size_t)(2 + gr) * N, col0);
 }
@@ -690,6 +765,8 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
   const int gr = blockIdx.y;
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
+  __shared__ uint2 stw[256];
+  stage_tw(stw, K.T.blk_tw(i), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
@@ -699,23 +776,25 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    lds_blk4_store(s, e, twist4(*reinterpret_cast<const uint4*>(u + e),
+    lds_blk4_store(s, e, twist4(ld4(u + e),
                                 K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, K.T.blk_tw(i), q, q2);
+  blk_stages<false>(s, stw, q, q2);
   __syncthreads();
   const uint2 qi = ldc(K.rescale_inv + (size_t)J.L * K.T.L_max + i);
   const uint32_t* a = J.a + ((size_t)c * J.L + i) * N + base;
   uint32_t* out = J.out + ((size_t)c * L1 + i) * N + base;
+  uint4 xs[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) xs[kk] = ld4(a + blk_elem(kk));
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
     const uint4 v = canon4(lds_blk4(s, e), q, q2);
-    const uint4 x = *reinterpret_cast<const uint4*>(a + e);
-    *reinterpret_cast<uint4*>(out + e) =
-        make_uint4(csub(mul_shoup(x.x + q - v.x, qi.x, qi.y, q), q), csub(mul_shoup(x.y + q - v.y, qi.x, qi.y, q), q),
-                   csub(mul_shoup(x.z + q - v.z, qi.x, qi.y, q), q), csub(mul_shoup(x.w + q - v.w, qi.x, qi.y, q), q));
+    const uint4 x = xs[kk];
+    st4(out + e, make_uint4(csub(mul_shoup(x.x + q - v.x, qi.x, qi.y, q), q), csub(mul_shoup(x.y + q - v.y, qi.x, qi.y, q), q),
+                   csub(mul_shoup(x.z + q - v.z, qi.x, qi.y, q), q), csub(mul_shoup(x.w + q - v.w, qi.x, qi.y, q), q)));
   }
 }
 

@@ -197,6 +197,13 @@ __device__ __forceinline__ void col_quad(int k, int& pos, int& c) {
   c = lin & (G::C - 1);
 }
 
+// Copy one prime's twiddle table of n <= kWG entries into LDS (the caller's
+// next __syncthreads() publishes it).  Issued with the tile's own loads, so
+// that no transform phase waits on a global load of its twiddles.
+__device__ __forceinline__ void stage_tw(uint2* stw, const uint2* __restrict__ tw, int n) {
+  if ((int)threadIdx.x < n) stw[threadIdx.x] = tw[threadIdx.x];
+}
+
 template <int LOGN1>
 __device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restrict__ row, int col0) {
   using G = ColGeom<LOGN1>;
@@ -204,7 +211,7 @@ __device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restric
   for (int k = 0; k < G::QUADS; ++k) {
     int pos, c;
     col_quad<LOGN1>(k, pos, c);
-    const uint4 v = *reinterpret_cast<const uint4*>(row + pos * 256 + col0 + c);
+    const uint4 v = ld4(row + pos * 256 + col0 + c);
     *reinterpret_cast<uint4*>(s + lidx_col(pos, c, G::C)) = v;
   }
 }
@@ -216,8 +223,7 @@ __device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restri
   for (int k = 0; k < G::QUADS; ++k) {
     int pos, c;
     col_quad<LOGN1>(k, pos, c);
-    *reinterpret_cast<uint4*>(row + pos * 256 + col0 + c) =
-        *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, G::C));
+    st4(row + pos * 256 + col0 + c, *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, G::C)));
   }
 }
 
