@@ -195,3 +195,27 @@ def test_errors_are_reported_not_launched():
     with pytest.raises(P.CkksError) as ex:
         P.ckks_modup(e.h, dev(np.zeros((4, e.N), np.uint32)), 4, empty(4, 5, e.N), small)
     assert ex.value.code == -2
+
+
+# ---------------------------------------------------------------- every ring degree / digit shape
+# The fused pipeline is compiled per column-pass shape (N = 2^12 .. 2^16) and per
+# digit size; these cases reach the shapes the cases above do not: N = 2^13,
+# 2^14, 2^15 on the 36 + 12 chain (partial and full digits) and the toy chain
+# (N = 2^12, 6 + 2 primes, digit size 2, three digits).
+@pytest.mark.parametrize("name,logN,L", [("n16_l36", 13, 7), ("n16_l36", 14, 13), ("n16_l36", 15, 30),
+                                         ("toy_n12", None, 6), ("toy_n12", None, 3)])
+def test_hmult_hrot_rescale_every_shape(name, logN, L):
+    e = env(name, logN)
+    ct1 = e.rng.polys(2, e.Q(L), e.N)
+    ct2 = e.rng.polys(2, e.Q(L), e.N)
+    key = e.rng.evk(e.spec)
+    out = empty(2, L, e.N)
+    P.ckks_hmult(e.h, dev(ct1), dev(ct2), L, dev(key), out, e.ctx.workspace("HMULT", L))
+    assert_same(host(out), O.hmult(e.par, ct1, ct2, L, key), f"hmult N=2^{e.spec.logN} L={L}")
+    rot = e.rng.rotation(e.N)
+    P.ckks_hrot(e.h, dev(ct1), L, rot, dev(key), out, e.ctx.workspace("HROT", L))
+    assert_same(host(out), O.hrot(e.par, ct1, L, rot, key), f"hrot N=2^{e.spec.logN} L={L}")
+    if L >= 2:
+        res = empty(2, L - 1, e.N)
+        P.ckks_rescale(e.h, dev(ct1), L, res, e.ctx.workspace("RESCALE", L))
+        assert_same(host(res), O.rescale(e.par, ct1, L), f"rescale N=2^{e.spec.logN} L={L}")
