@@ -410,12 +410,14 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   // loads, so that their latency overlaps the transforms below.
   constexpr int KPF = 2;
   uint4 kpre0[KPF][NB], kpre1[KPF][NB];
+  // (no branch here: a control-flow merge would make the compiler wait for
+  // these loads; digits past beta re-read the last digit's rows, unused)
 #pragma unroll
   for (int kk = 0; kk < KPF; ++kk)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      if (j >= V.beta) break;
-      const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pi) * N + base + blk_elem(kk);
+      const int jj = min(j, V.beta - 1);
+      const uint32_t* k0 = J.key + ((size_t)jj * 2 * KR + pi) * N + base + blk_elem(kk);
       kpre0[kk][j] = ld4(k0);
       kpre1[kk][j] = ld4(k0 + KR * N);
     }
