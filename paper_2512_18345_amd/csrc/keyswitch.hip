@@ -204,20 +204,28 @@ __global__ __launch_bounds__(kWG) void k3_bconv_up(KsConst K, JobArg<KsJob> JA, 
   const KsView V = ks_view(J, K, N);
   if (j >= V.beta || g * RB >= V.R) return;
   const int lo = j * ALPHA, hi = min(lo + ALPHA, V.L);
-  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
-  uint32_t x[ALPHA];
+  const size_t n = ((size_t)blockIdx.x * kWG + threadIdx.x) * 4;  // four coefficients per thread
+  uint4 x[ALPHA];
 #pragma unroll
-  for (int i = 0; i < ALPHA; ++i) x[i] = ld1(V.y + (size_t)min(lo + i, V.L - 1) * N + n);
+  for (int i = 0; i < ALPHA; ++i) x[i] = ld4(V.y + (size_t)min(lo + i, V.L - 1) * N + n);
   const uint32_t* Tt = K.modup_T + ldc(K.modup_T_off + (size_t)V.L * K.beta_max + j);
   const int r1 = min(g * RB + RB, V.R);
   for (int r = g * RB; r < r1; ++r) {
     if (r >= lo && r < hi) continue;
     const ModC m = ldc(K.T.mod + ks_pidx(r, V.L, K.T.L_max));
     const uint32_t* t = Tt + (size_t)r * ALPHA;
-    uint64_t acc = 0;
+    uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
-    for (int i = 0; i < ALPHA; ++i) acc += (uint64_t)x[i] * ldc(t + i);
-    st1(V.z + ((size_t)j * V.R + r) * N + n, reduce64(acc, m.q, m.mu_hi, m.mu_lo));
+    for (int i = 0; i < ALPHA; ++i) {
+      const uint64_t ti = ldc(t + i);
+      a0 += x[i].x * ti;
+      a1 += x[i].y * ti;
+      a2 += x[i].z * ti;
+      a3 += x[i].w * ti;
+    }
+    st4(V.z + ((size_t)j * V.R + r) * N + n,
+        make_uint4(reduce64(a0, m.q, m.mu_hi, m.mu_lo), reduce64(a1, m.q, m.mu_hi, m.mu_lo),
+                   reduce64(a2, m.q, m.mu_hi, m.mu_lo), reduce64(a3, m.q, m.mu_hi, m.mu_lo)));
   }
 }
 
@@ -542,18 +550,26 @@ __global__ __launch_bounds__(kWG) void k7_bconv_down(KsConst K, JobArg<KsJob> JA
   const KsView V = ks_view(J, K, N);
   const int c = blockIdx.y / groups, g = blockIdx.y % groups;
   if (g * RB >= V.L) return;
-  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
-  uint32_t x[KP];
+  const size_t n = ((size_t)blockIdx.x * kWG + threadIdx.x) * 4;  // four coefficients per thread
+  uint4 x[KP];
 #pragma unroll
-  for (int mm = 0; mm < KP; ++mm) x[mm] = ld1(V.x + ((size_t)c * KP + mm) * N + n);
+  for (int mm = 0; mm < KP; ++mm) x[mm] = ld4(V.x + ((size_t)c * KP + mm) * N + n);
   const int r1 = min(g * RB + RB, V.L);
   for (int i = g * RB; i < r1; ++i) {
     const ModC m = ldc(K.T.mod + i);
     const uint32_t* t = K.moddown_T + (size_t)i * KP;
-    uint64_t acc = 0;
+    uint64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
-    for (int mm = 0; mm < KP; ++mm) acc += (uint64_t)x[mm] * ldc(t + mm);
-    st1(V.w + ((size_t)c * V.L + i) * N + n, reduce64(acc, m.q, m.mu_hi, m.mu_lo));
+    for (int mm = 0; mm < KP; ++mm) {
+      const uint64_t tm = ldc(t + mm);
+      a0 += x[mm].x * tm;
+      a1 += x[mm].y * tm;
+      a2 += x[mm].z * tm;
+      a3 += x[mm].w * tm;
+    }
+    st4(V.w + ((size_t)c * V.L + i) * N + n,
+        make_uint4(reduce64(a0, m.q, m.mu_hi, m.mu_lo), reduce64(a1, m.q, m.mu_hi, m.mu_lo),
+                   reduce64(a2, m.q, m.mu_hi, m.mu_lo), reduce64(a3, m.q, m.mu_hi, m.mu_lo)));
   }
 }
 
@@ -814,7 +830,8 @@ size_t ks_hoist_ws_words(const Ctx& c, int L) {
 size_t rs_ws_words(const Ctx& c, int L) { return (2 + 2 * (size_t)L) * c.N; }
 
 namespace {
-constexpr int kRB = 12;  // BConv output rows per work-group (inputs re-read once per group)
+constexpr int kRB = 12;  // ModUp BConv output rows per work-group (inputs re-read once per group)
+constexpr int kRB7 = 6;  // ModDown BConv: fewer rows per work-group, so that L = 36 still gives 768 of them
 
 // Launch of a pipeline kernel; when its stage is traced, the trace events
 // are attached to the dispatch itself.
@@ -837,7 +854,7 @@ template <int A>
 struct K7 {
   static void run(const Ctx& c, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
                   int gr) {
-    klaunch(c, CKKS_STAGE_BCONV_DOWN, k7_bconv_down<A, kRB>, g, st, K, J, gr);
+    klaunch(c, CKKS_STAGE_BCONV_DOWN, k7_bconv_down<A, kRB7>, g, st, K, J, gr);
   }
 };
 
@@ -860,10 +877,10 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
                        int Lmax, bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp) {
   const int Rmax = Lmax + c.k;
   const int tiles = c.N / kTile;
-  const int cols = c.N / kWG;
+  const int cols = c.N / (4 * kWG);  // BConv: four coefficients per thread
   const int bmax = c.beta(Lmax);
   const int up_groups = (Rmax + kRB - 1) / kRB;
-  const int down_groups = (Lmax + kRB - 1) / kRB;
+  const int down_groups = (Lmax + kRB7 - 1) / kRB7;
   hipError_t e;
   if (with_modup) {
     klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1>, dim3(tiles, Lmax, njobs), st, K, jobs);
