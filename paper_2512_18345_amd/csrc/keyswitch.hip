@@ -627,57 +627,47 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
   const size_t L = V.L;
   const bool hmult = J.kind == KS_HMULT;
   const bool rot = (J.kind == KS_HROT || J.kind == KS_HOIST) && c == 0;
-  // all loads first (a store to out could alias a later load), then the combine
-  uint4 av[4], x0[4], y0[4], x1[4], y1[4];
-  uint32_t g[4][4];
+  // Loads first (a store to out could alias a later load): the accumulator
+  // quads and the term this component adds — d0 = c0 c0' or d1 = c0 c1' + c1 c0'
+  // (HMULT, formed here from the inputs), sigma(c0) (rotations, c = 0), else 0.
+  // The term is formed as soon as its words arrive, so at most one quad's
+  // inputs are live at a time.
+  uint4 av[4], dv[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
     const uint32_t n = base + e;
     av[kk] = ld4(accr + e);
+    dv[kk] = make_uint4(0, 0, 0, 0);
     if (hmult) {
-      x0[kk] = ld4(J.a + i * N + n);
-      y0[kk] = ld4(J.b + i * N + n);
-      if (c == 1) {
-        x1[kk] = ld4(J.a + (L + i) * N + n);
-        y1[kk] = ld4(J.b + (L + i) * N + n);
+      const uint4 xa = ld4(J.a + i * N + n), ya = ld4(J.b + i * N + n);
+      if (c == 0) {
+        dv[kk] = make_uint4(mulmod(xa.x, ya.x, m), mulmod(xa.y, ya.y, m), mulmod(xa.z, ya.z, m),
+                            mulmod(xa.w, ya.w, m));
+      } else {
+        const uint4 xb = ld4(J.a + (L + i) * N + n), yb = ld4(J.b + (L + i) * N + n);
+        dv[kk] = make_uint4(
+            reduce64((uint64_t)xa.x * yb.x + (uint64_t)xb.x * ya.x, q, m.mu_hi, m.mu_lo),
+            reduce64((uint64_t)xa.y * yb.y + (uint64_t)xb.y * ya.y, q, m.mu_hi, m.mu_lo),
+            reduce64((uint64_t)xa.z * yb.z + (uint64_t)xb.z * ya.z, q, m.mu_hi, m.mu_lo),
+            reduce64((uint64_t)xa.w * yb.w + (uint64_t)xb.w * ya.w, q, m.mu_hi, m.mu_lo));
       }
     } else if (rot) {
       const uint32_t* c0 = J.a + i * N;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) g[kk][t] = ld1(c0 + auto_src(n + t, J.gal, logN));
+      dv[kk] = make_uint4(ld1(c0 + auto_src(n, J.gal, logN)), ld1(c0 + auto_src(n + 1, J.gal, logN)),
+                          ld1(c0 + auto_src(n + 2, J.gal, logN)), ld1(c0 + auto_src(n + 3, J.gal, logN)));
     }
   }
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
     const uint4 w = canon4(lds_blk4(s, e), q, q2);
-    const uint4 a = av[kk];
-    uint32_t o[4] = {a.x + q - w.x, a.y + q - w.y, a.z + q - w.z, a.w + q - w.w};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) o[t] = csub(mul_shoup(o[t], pv.x, pv.y, q), q);
-    if (hmult) {
-      // d0 = c0 c0' (c = 0) or d1 = c0 c1' + c1 c0' (c = 1), formed here from the inputs
-      const uint32_t xa[4] = {x0[kk].x, x0[kk].y, x0[kk].z, x0[kk].w};
-      const uint32_t ya[4] = {y0[kk].x, y0[kk].y, y0[kk].z, y0[kk].w};
-      if (c == 0) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) o[t] = csub(o[t] + mulmod(xa[t], ya[t], m), q);
-      } else {
-        const uint32_t xb[4] = {x1[kk].x, x1[kk].y, x1[kk].z, x1[kk].w};
-        const uint32_t yb[4] = {y1[kk].x, y1[kk].y, y1[kk].z, y1[kk].w};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const uint32_t d1 =
-              reduce64((uint64_t)xa[t] * yb[t] + (uint64_t)xb[t] * ya[t], q, m.mu_hi, m.mu_lo);
-          o[t] = csub(o[t] + d1, q);
-        }
-      }
-    } else if (rot) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) o[t] = csub(o[t] + g[kk][t], q);
-    }
-    st4(out + e, make_uint4(o[0], o[1], o[2], o[3]));
+    const uint4 a = av[kk], d = dv[kk];
+    const uint32_t o0 = csub(mul_shoup(a.x + q - w.x, pv.x, pv.y, q), q);
+    const uint32_t o1 = csub(mul_shoup(a.y + q - w.y, pv.x, pv.y, q), q);
+    const uint32_t o2 = csub(mul_shoup(a.z + q - w.z, pv.x, pv.y, q), q);
+    const uint32_t o3 = csub(mul_shoup(a.w + q - w.w, pv.x, pv.y, q), q);
+    st4(out + e, make_uint4(csub(o0 + d.x, q), csub(o1 + d.y, q), csub(o2 + d.z, q), csub(o3 + d.w, q)));
   }
 }
 
