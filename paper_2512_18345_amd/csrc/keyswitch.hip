@@ -887,7 +887,7 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   // streaming, HBM-heavy) runs on the side stream; K9 joins both.
   auto k5 = [&](int stage, int part, hipStream_t s5, int rows) {
     const dim3 g5(tiles, rows, njobs);
-    switch (std::max(c.beta_max(), 2)) {
+    switch (std::max(c.beta(Lmax), 2)) {  // slots for the launch's own largest digit count
       case 2: klaunch(c, stage, k5s_ntt_blks_ip<L1, 2>, g5, s5, K, jobs, part); break;
       case 3: klaunch(c, stage, k5s_ntt_blks_ip<L1, 3>, g5, s5, K, jobs, part); break;
       case 4: klaunch(c, stage, k5s_ntt_blks_ip<L1, 4>, g5, s5, K, jobs, part); break;
