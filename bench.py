@@ -70,6 +70,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--small-reps", type=int, default=10000,
+                    help="HMult latency samples at N=2^12, 4+1 primes, dnum 4 (0 = skip)")
+    ap.add_argument("--serve-budgets", type=str, default="0.25,1,64",
+                    help="HBM budgets (GiB) of the extra saturated serving runs")
     ap.add_argument("--boot-trace", action="store_true",
                     help="only run the bootstrapping-shaped operation trace (132 key-switches)")
     ap.add_argument("--serve", action="store_true",
@@ -180,6 +184,7 @@ def main():
         e1.synchronize()
         lat.append(e0.elapsed_time(e1) * 1e3)
     lat = np.array(lat)
+    small = None if args.small_reps <= 0 else small_hmult_latency(P, ci, args.small_reps)
 
     beta = ctx.beta(L)
     R = L + k
@@ -235,6 +240,7 @@ def main():
         "hmult_latency_us": {"p50": round(float(np.percentile(lat, 50)), 2),
                              "p99": round(float(np.percentile(lat, 99)), 2),
                              "reps": int(len(lat))},
+        "hmult_latency_us_n12_l4": small,
         "path": path,
         "batched": batched,
         "roofline": roofline,
@@ -242,6 +248,41 @@ def main():
     }
     print(json.dumps(rec), flush=True)
     ctx.close()
+
+
+def small_hmult_latency(P, ci, reps):
+    """Latency distribution of one HMult at N=2^12 with 4 + 1 primes, dnum 4:
+    each call bracketed by events on its stream (a launch-latency-bound case)."""
+    import torch
+    spec = ci.get("n12_l4")
+    rng = ci.Rng(spec.seed)
+    L = spec.L_max
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32).copy()).cuda()
+
+    ct1, ct2 = dev(rng.polys(2, spec.q, spec.N)), dev(rng.polys(2, spec.q, spec.N))
+    rlk = dev(rng.evk(spec))
+    ctx = P.Context.from_spec(spec)
+    ws = ctx.workspace("HMULT", L)
+    out = torch.empty((2, L, spec.N), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(20):
+        P.ckks_hmult(ctx.handle, ct1, ct2, L, rlk, out, ws, stream)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.ckks_hmult(ctx.handle, ct1, ct2, L, rlk, out, ws, stream)
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1) * 1e3)
+    lat = np.array(lat)
+    ctx.close()
+    return {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+            "reps": int(reps)}
 
 
 def _op_limbs(op, L, k, beta):
@@ -424,7 +465,7 @@ def serve_bench(args):
                 jobs.append(dict(op=op, L=L, in0=a1, in1=a2, key=keys[c], out=o))
         return c, jobs
 
-    def run(n_req, rate, seed):
+    def run(n_req, rate, seed, srv):
         r = random.Random(seed)
         reqs = [make_request(r) for _ in range(n_req)]
         first = P.ckks_server_stats(srv)["submitted"]
@@ -454,15 +495,25 @@ def serve_bench(args):
                 "p50_us": round(float(np.percentile(lat, 50)), 1),
                 "p99_us": round(float(np.percentile(lat, 99)), 1)}
 
-    run(20, 0, 1)  # warm-up
-    sat = run(args.serve_requests, 0, 2)
+    run(20, 0, 1, srv)  # warm-up
+    sat = run(args.serve_requests, 0, 2, srv)
     mean_b = 16.5
     loads = {}
     for rho in (0.5, 0.8, 0.95):
-        loads[str(rho)] = run(args.serve_requests, rho * sat["jobs_per_s"] / mean_b, 3 + int(rho * 100))
+        loads[str(rho)] = run(args.serve_requests, rho * sat["jobs_per_s"] / mean_b, 3 + int(rho * 100), srv)
     st = P.ckks_server_stats(srv)
     P.ckks_server_destroy(srv)
-    print(json.dumps({"serving": {"saturated": sat, "poisson": loads, "max_slots": max_slots,
+    # saturated throughput under smaller HBM budgets (admission by scratch bytes)
+    budgets = {}
+    for gib in [float(v) for v in args.serve_budgets.split(",") if v.strip()]:
+        s2 = P.ckks_server_create([c.handle for c in ctxs], int(gib * (1 << 30)), max_slots)
+        r = run(max(args.serve_requests // 2, 20), 0, 7, s2)
+        st2 = P.ckks_server_stats(s2)
+        r.update(peak_bytes=st2["peak_bytes"], batches=st2["batches"], rejected=st2["rejected"])
+        budgets[str(gib)] = r
+        P.ckks_server_destroy(s2)
+    print(json.dumps({"serving": {"saturated": sat, "poisson": loads, "budget_sweep_gib": budgets,
+                                  "max_slots": max_slots,
                                   "budget_bytes": st["budget_bytes"], "peak_bytes": st["peak_bytes"],
                                   "batches": st["batches"]}}), flush=True)
 
