@@ -430,14 +430,18 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
       kpre1[kk][j] = ld4(k0 + KR * N);
     }
   __syncthreads();
+  // The block-pass transforms of all digit tiles, phase by phase: the tiles
+  // share the prime, so each phase's twiddles are fetched once for all of
+  // them, and there are two barrier intervals instead of two per tile.
+  const uint2* tw = K.T.blk_tw(pi);
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    if (j >= V.beta) break;
-    const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
-    if (!(r >= lo && r < hi)) {
-      blk_stages<false>(s + j * kLds, K.T.blk_tw(pi), q, q2);
-      __syncthreads();
+  for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
+      if (j < V.beta && !(r >= lo && r < hi)) blk_phase<4, false>(s + j * kLds, ph ? 0 : 4, tw, q, q2);
     }
+    __syncthreads();
   }
 
   // inner product, one quad at a time (one reduction per output, Sec. III-C2)
