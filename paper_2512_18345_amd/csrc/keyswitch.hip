@@ -414,9 +414,12 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
       }
     }
   }
-  // The key words of the first KPF quads are requested now, after the digit
-  // loads, so that their latency overlaps the transforms below.
-  constexpr int KPF = 2;
+  // The block-pass twiddles go to the pads of slots 0 and 1, so the
+  // transforms issue no global load.  The key words of the first KPF quads
+  // are requested now, after the digit loads: their latency overlaps the
+  // transforms below (all four quads would cost a resident work-group).
+  stage_tw_pads(s, K.T.blk_tw(pi));
+  constexpr int KPF = NB <= 2 ? 4 : 2;
   uint4 kpre0[KPF][NB], kpre1[KPF][NB];
   // (no branch here: a control-flow merge would make the compiler wait for
   // these loads; digits past beta re-read the last digit's rows, unused)
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   // The block-pass transforms of all digit tiles, phase by phase: the tiles
   // share the prime, so each phase's twiddles are fetched once for all of
   // them, and there are two barrier intervals instead of two per tile.
-  const uint2* tw = K.T.blk_tw(pi);
+  const PadTw tw{s};
 #pragma unroll
   for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll
@@ -444,7 +447,9 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
     __syncthreads();
   }
 
-  // inner product, one quad at a time (one reduction per output, Sec. III-C2)
+  // inner product, one quad at a time (one reduction per output, Sec. III-C2).
+  // No branch on the digit count: tiles past beta (never staged) are masked
+  // to zero, so the prefetched key words are consumed in straight-line code.
   uint4 res0[4], res1[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -452,14 +457,18 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
     uint64_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      if (j >= V.beta) break;
-      const uint4 v = canon4(lds_blk4(s + j * kLds, e), q, q2);
+      const uint32_t msk = j < V.beta ? ~0u : 0u;
+      uint4 v = canon4(lds_blk4(s + j * kLds, e), q, q2);
+      v.x &= msk;
+      v.y &= msk;
+      v.z &= msk;
+      v.w &= msk;
       uint4 e0, e1;
       if (kk < KPF) {
         e0 = kpre0[kk][j];
         e1 = kpre1[kk][j];
       } else {
-        const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pi) * N + base + e;
+        const uint32_t* k0 = J.key + ((size_t)min(j, V.beta - 1) * 2 * KR + pi) * N + base + e;
         e0 = ld4(k0);
         e1 = ld4(k0 + KR * N);
       }
@@ -488,17 +497,19 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
     }
     return;
   }
-  // P rows: the INTT block pass of ModDown on both components (slots 0 and 1)
-  // (twiddles from global memory: 2 KB more LDS would cost a resident work-group)
+  // P rows: the INTT block pass of ModDown on both components (slots 0 and 1),
+  // inverse twiddles in the same pads (the forward ones were last read before
+  // the barrier that ended the transforms)
   __syncthreads();
+  stage_tw_pads(s, K.T.blk_itw(pi));
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     lds_blk4_store(s, blk_elem(kk), res0[kk]);
     lds_blk4_store(s + kLds, blk_elem(kk), res1[kk]);
   }
   __syncthreads();
-  blk_stages<true>(s, K.T.blk_itw(pi), q, q2);
-  blk_stages<true>(s + kLds, K.T.blk_itw(pi), q, q2);
+  blk_stages<true>(s, PadTw{s}, q, q2);
+  blk_stages<true>(s + kLds, PadTw{s}, q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {

@@ -34,6 +34,29 @@ struct ColGeom {
 __device__ __forceinline__ int lidx_col(int pos, int c, int C) { return pos * C + c + ((pos >> 4) << 4); }
 __device__ __forceinline__ int lidx_blk(int line, int pos) { return line * 272 + pos + (pos >> 4); }
 
+// The block layout leaves one unused word after every 16 data words: 256 pad
+// words per tile, at line * 272 + 17 m + 16 (m < 16).  A 256-entry twiddle
+// table of (w, w') pairs fits in the pads of two consecutive tiles: pad
+// number u (< 512) holds word u % 2 of entry u / 2.  The data path never
+// touches the pads, so a kernel whose LDS is full of tiles can still read its
+// twiddles from LDS.
+__device__ __forceinline__ int lidx_pad(int u) {
+  return (u >> 8) * kLds + ((u >> 4) & 15) * 272 + 17 * (u & 15) + 16;
+}
+struct PadTw {
+  const uint32_t* s;  // first of the two tiles
+  __device__ __forceinline__ uint2 operator[](int i) const {
+    return make_uint2(s[lidx_pad(2 * i)], s[lidx_pad(2 * i + 1)]);
+  }
+};
+// Copy a prime's 256-entry block-pass table into the pads of tiles s, s + kLds
+// (the caller's next __syncthreads() publishes it).
+__device__ __forceinline__ void stage_tw_pads(uint32_t* s, const uint2* __restrict__ tw) {
+  const uint2 w = tw[threadIdx.x];
+  s[lidx_pad(2 * threadIdx.x)] = w.x;
+  s[lidx_pad(2 * threadIdx.x + 1)] = w.y;
+}
+
 // ----- column-pass phases (stages on pos bits [blo, blo + LOGR)) -----------
 template <int LOGR, bool INV, int ELEMS>
 __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo,
@@ -83,9 +106,10 @@ __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo
 // After the twist the 256-word block transform is the same for every block:
 // the pair on pos bit beta uses ctw[(1 << (7 - beta)) | (pos >> (beta + 1))],
 // and its stage on bit 7 (first forward / last inverse) multiplies by 1.
-template <int LOGR, bool INV>
-__device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const uint2* __restrict__ tw,
-                                          uint32_t q, uint32_t q2) {
+// TW: a twiddle table indexable as tw[i] -> uint2 (a pointer, or PadTw below).
+template <int LOGR, bool INV, class TW>
+__device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, uint32_t q,
+                                          uint32_t q2) {
   constexpr int R = 1 << LOGR;
   constexpr int GPT = 16 / R;
   constexpr int NB = 8 - LOGR;
@@ -160,8 +184,8 @@ __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_
   }
 }
 
-template <bool INV>
-__device__ __forceinline__ void blk_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
+template <bool INV, class TW>
+__device__ __forceinline__ void blk_stages(uint32_t* s, const TW& tw, uint32_t q, uint32_t q2) {
   if (!INV) {
     blk_phase<4, false>(s, 4, tw, q, q2);
     __syncthreads();
