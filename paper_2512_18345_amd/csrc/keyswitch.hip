@@ -520,6 +520,122 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   }
 }
 
+// K5 for small grids (few tiles x rows, e.g. N = 2^12): one 1024-thread
+// work-group per (tile, row).  Thread group d = threadIdx.x / 256 stages and
+// transforms digit tile d, so the digits' transforms run side by side; then
+// every thread forms the inner product of one quad over all digits.  Every
+// barrier below is reached by all threads of the work-group.
+constexpr int kWGP = 4 * kWG;
+template <int LOGN1, int NB>
+__global__ __launch_bounds__(kWGP) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob> JA, int part) {
+  static_assert(NB >= 2 && NB <= 4, "one thread group per digit tile");
+  const KsJob J = JA.get(blockIdx.z);
+  const int logN = K.T.logN;
+  const size_t N = (size_t)1 << logN;
+  const KsView V = ks_view(J, K, N);
+  const int r = blockIdx.y + (part == KS_PART_P ? V.L : 0);
+  if (r >= V.R || (part == KS_PART_Q && r >= V.L) || J.kind == KS_HOIST) return;
+  __shared__ __align__(16) uint32_t s[NB * kLds];
+  const int pi = ks_pidx(r, V.L, K.T.L_max);
+  const ModC m = ldc(K.T.mod + pi);
+  const uint32_t q = m.q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t base = blk0 * 256;
+  const size_t KR = (size_t)K.T.L_max + K.k;  // key rows
+  const int grp = threadIdx.x / kWG, lt = threadIdx.x % kWG;
+  // digit this thread group owns, and whether its tile needs the transform
+  const int lo = grp * K.alpha, hi = min(lo + K.alpha, V.L);
+  const bool have = grp < NB && grp < V.beta;
+  const bool own = r >= lo && r < hi;
+  if (have) {
+    uint32_t* slot = s + grp * kLds;
+    uint4 v[4];
+    if (own) {
+      const uint32_t* drow = (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(drow + (lt + kk * kWG) * 4);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) lds_blk4_store(slot, (lt + kk * kWG) * 4, v[kk]);
+    } else {
+      const uint32_t* zrow = V.z + ((size_t)grp * V.R + r) * N + base;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(zrow + (lt + kk * kWG) * 4);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int e = (lt + kk * kWG) * 4;
+        lds_blk4_store(slot, e, twist4(v[kk], K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
+      }
+    }
+  }
+  if (grp == 0) stage_tw_pads(s, K.T.blk_tw(pi), lt);
+  // key words of this thread's quad, requested before the transforms
+  const int e = threadIdx.x * 4;
+  uint4 k0v[NB], k1v[NB];
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) {
+    const uint32_t* k0 = J.key + ((size_t)min(jj, V.beta - 1) * 2 * KR + pi) * N + base + e;
+    k0v[jj] = ld4(k0);
+    k1v[jj] = ld4(k0 + KR * N);
+  }
+  __syncthreads();
+  const PadTw tw{s};
+  if (have && !own) blk_phase<4, false>(s + grp * kLds, 4, tw, q, q2, lt);
+  __syncthreads();
+  if (have && !own) blk_phase<4, false>(s + grp * kLds, 0, tw, q, q2, lt);
+  __syncthreads();
+
+  // inner product of quad e over the digits (one reduction per output)
+  uint64_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) {
+    const uint32_t msk = jj < V.beta ? ~0u : 0u;
+    uint4 v = canon4(lds_blk4(s + jj * kLds, e), q, q2);
+    v.x &= msk;
+    v.y &= msk;
+    v.z &= msk;
+    v.w &= msk;
+    a0[0] += (uint64_t)v.x * k0v[jj].x;
+    a0[1] += (uint64_t)v.y * k0v[jj].y;
+    a0[2] += (uint64_t)v.z * k0v[jj].z;
+    a0[3] += (uint64_t)v.w * k0v[jj].w;
+    a1[0] += (uint64_t)v.x * k1v[jj].x;
+    a1[1] += (uint64_t)v.y * k1v[jj].y;
+    a1[2] += (uint64_t)v.z * k1v[jj].z;
+    a1[3] += (uint64_t)v.w * k1v[jj].w;
+  }
+  const uint4 res0 = make_uint4(reduce64(a0[0], q, m.mu_hi, m.mu_lo), reduce64(a0[1], q, m.mu_hi, m.mu_lo),
+                                reduce64(a0[2], q, m.mu_hi, m.mu_lo), reduce64(a0[3], q, m.mu_hi, m.mu_lo));
+  const uint4 res1 = make_uint4(reduce64(a1[0], q, m.mu_hi, m.mu_lo), reduce64(a1[1], q, m.mu_hi, m.mu_lo),
+                                reduce64(a1[2], q, m.mu_hi, m.mu_lo), reduce64(a1[3], q, m.mu_hi, m.mu_lo));
+  uint32_t* acc0 = V.acc + (size_t)r * N + base;
+  uint32_t* acc1 = V.acc + ((size_t)V.R + r) * N + base;
+  if (r < V.L) {  // uniform over the work-group
+    st4(acc0 + e, res0);
+    st4(acc1 + e, res1);
+    return;
+  }
+  // P rows: the INTT block pass of ModDown, component c in slot c by thread
+  // group c; inverse twiddles in the same pads (the forward ones were last
+  // read before the previous barrier)
+  __syncthreads();
+  lds_blk4_store(s, e, res0);
+  lds_blk4_store(s + kLds, e, res1);
+  if (grp == 0) stage_tw_pads(s, K.T.blk_itw(pi), lt);
+  __syncthreads();
+  if (grp < 2) blk_phase<4, true>(s + grp * kLds, 0, PadTw{s}, q, q2, lt);
+  __syncthreads();
+  if (grp < 2) blk_phase<4, true>(s + grp * kLds, 4, PadTw{s}, q, q2, lt);
+  __syncthreads();
+  if (grp < 2) {
+    uint32_t* dst = grp ? acc1 : acc0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int ee = (lt + kk * kWG) * 4;
+      st4(dst + ee, twist4(lds_blk4(s + grp * kLds, ee), K.T.blk_itwist(pi, blk0 + (ee >> 8)), ee & 255, q));
+    }
+  }
+}
+
 // ============================================================================
 // Stage 3: ModDown of both components
 // ============================================================================
@@ -836,15 +952,21 @@ size_t rs_ws_words(const Ctx& c, int L) { return (2 + 2 * (size_t)L) * c.N; }
 
 namespace {
 constexpr int kRB = 12;  // ModUp BConv output rows per work-group (inputs re-read once per group)
-constexpr int kRB7 = 6;  // ModDown BConv: fewer rows per work-group, so that L = 36 still gives 768 of them
+constexpr int kRB7 = 6;
+// K5 grids up to this many work-groups use the one-group-per-digit variant.
+constexpr int kSmallGrid = 128;  // ModDown BConv: fewer rows per work-group, so that L = 36 still gives 768 of them
 
 // Launch of a pipeline kernel; when its stage is traced, the trace events
 // are attached to the dispatch itself.
 template <typename F, typename... A>
-void klaunch(const Ctx& c, int stage, F kern, dim3 g, hipStream_t st, A... args) {
+void klaunch_b(const Ctx& c, int stage, F kern, dim3 g, int block, hipStream_t st, A... args) {
   hipEvent_t t0, t1;
   c.trace_take(stage, &t0, &t1);
-  hipExtLaunchKernelGGL(kern, g, dim3(kWG), 0, st, t0, t1, 0, args...);
+  hipExtLaunchKernelGGL(kern, g, dim3(block), 0, st, t0, t1, 0, args...);
+}
+template <typename F, typename... A>
+void klaunch(const Ctx& c, int stage, F kern, dim3 g, hipStream_t st, A... args) {
+  klaunch_b(c, stage, kern, g, kWG, st, args...);
 }
 
 // Dispatch a small compile-time count (digit size or special-prime count, 1..16).
@@ -902,7 +1024,16 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   // streaming, HBM-heavy) runs on the side stream; K9 joins both.
   auto k5 = [&](int stage, int part, hipStream_t s5, int rows) {
     const dim3 g5(tiles, rows, njobs);
-    switch (std::max(c.beta(Lmax), 2)) {  // slots for the launch's own largest digit count
+    const int nb = std::max(c.beta(Lmax), 2);  // slots for the launch's own largest digit count
+    if (tiles * rows * njobs <= kSmallGrid && nb <= 4) {  // too few work-groups to fill the CUs
+      switch (nb) {
+        case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2>, g5, kWGP, s5, K, jobs, part); break;
+        case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3>, g5, kWGP, s5, K, jobs, part); break;
+        default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4>, g5, kWGP, s5, K, jobs, part); break;
+      }
+      return;
+    }
+    switch (nb) {
       case 2: klaunch(c, stage, k5s_ntt_blks_ip<L1, 2>, g5, s5, K, jobs, part); break;
       case 3: klaunch(c, stage, k5s_ntt_blks_ip<L1, 3>, g5, s5, K, jobs, part); break;
       case 4: klaunch(c, stage, k5s_ntt_blks_ip<L1, 4>, g5, s5, K, jobs, part); break;

@@ -51,10 +51,11 @@ struct PadTw {
 };
 // Copy a prime's 256-entry block-pass table into the pads of tiles s, s + kLds
 // (the caller's next __syncthreads() publishes it).
-__device__ __forceinline__ void stage_tw_pads(uint32_t* s, const uint2* __restrict__ tw) {
-  const uint2 w = tw[threadIdx.x];
-  s[lidx_pad(2 * threadIdx.x)] = w.x;
-  s[lidx_pad(2 * threadIdx.x + 1)] = w.y;
+__device__ __forceinline__ void stage_tw_pads(uint32_t* s, const uint2* __restrict__ tw,
+                                              int tid = threadIdx.x) {
+  const uint2 w = tw[tid];
+  s[lidx_pad(2 * tid)] = w.x;
+  s[lidx_pad(2 * tid + 1)] = w.y;
 }
 
 // ----- column-pass phases (stages on pos bits [blo, blo + LOGR)) -----------
@@ -107,15 +108,16 @@ __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo
 // the pair on pos bit beta uses ctw[(1 << (7 - beta)) | (pos >> (beta + 1))],
 // and its stage on bit 7 (first forward / last inverse) multiplies by 1.
 // TW: a twiddle table indexable as tw[i] -> uint2 (a pointer, or PadTw below).
+// tid: the thread's index among the kWG threads that transform this tile.
 template <int LOGR, bool INV, class TW>
 __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, uint32_t q,
-                                          uint32_t q2) {
+                                          uint32_t q2, int tid = threadIdx.x) {
   constexpr int R = 1 << LOGR;
   constexpr int GPT = 16 / R;
   constexpr int NB = 8 - LOGR;
 #pragma unroll
   for (int gg = 0; gg < GPT; ++gg) {
-    const int g = threadIdx.x + gg * kWG;
+    const int g = tid + gg * kWG;
     const int rest = g & ((1 << NB) - 1);
     const int line = g >> NB;
     const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
@@ -185,15 +187,16 @@ __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_
 }
 
 template <bool INV, class TW>
-__device__ __forceinline__ void blk_stages(uint32_t* s, const TW& tw, uint32_t q, uint32_t q2) {
+__device__ __forceinline__ void blk_stages(uint32_t* s, const TW& tw, uint32_t q, uint32_t q2,
+                                           int tid = threadIdx.x) {
   if (!INV) {
-    blk_phase<4, false>(s, 4, tw, q, q2);
+    blk_phase<4, false>(s, 4, tw, q, q2, tid);
     __syncthreads();
-    blk_phase<4, false>(s, 0, tw, q, q2);
+    blk_phase<4, false>(s, 0, tw, q, q2, tid);
   } else {
-    blk_phase<4, true>(s, 0, tw, q, q2);
+    blk_phase<4, true>(s, 0, tw, q, q2, tid);
     __syncthreads();
-    blk_phase<4, true>(s, 4, tw, q, q2);
+    blk_phase<4, true>(s, 4, tw, q, q2, tid);
   }
 }
 
