@@ -267,17 +267,28 @@ struct PtrList16 {
 __global__ __launch_bounds__(kWG) void k_pmult_sum(DevTab T, PtrList16 cts, PtrList16 pts, int nb, int L,
                                                    uint32_t* out) {
   const size_t N = (size_t)1 << T.logN;
-  const size_t n = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const size_t n = ((size_t)blockIdx.x * kWG + threadIdx.x) * 4;  // four coefficients per thread
   const int i = blockIdx.y;
   const ModC m = ldc(T.mod + i);
-  uint64_t a0 = 0, a1 = 0;
+  uint64_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
   for (int b = 0; b < nb; ++b) {
-    const uint32_t pt = pts.p[b][(size_t)i * N + n];
-    a0 += (uint64_t)cts.p[b][(size_t)i * N + n] * pt;
-    a1 += (uint64_t)cts.p[b][((size_t)L + i) * N + n] * pt;
+    const uint4 pt = ld4(pts.p[b] + (size_t)i * N + n);
+    const uint4 x = ld4(cts.p[b] + (size_t)i * N + n);
+    const uint4 y = ld4(cts.p[b] + ((size_t)L + i) * N + n);
+    a0[0] += (uint64_t)x.x * pt.x;
+    a0[1] += (uint64_t)x.y * pt.y;
+    a0[2] += (uint64_t)x.z * pt.z;
+    a0[3] += (uint64_t)x.w * pt.w;
+    a1[0] += (uint64_t)y.x * pt.x;
+    a1[1] += (uint64_t)y.y * pt.y;
+    a1[2] += (uint64_t)y.z * pt.z;
+    a1[3] += (uint64_t)y.w * pt.w;
   }
-  out[(size_t)i * N + n] = reduce64(a0, m.q, m.mu_hi, m.mu_lo);
-  out[((size_t)L + i) * N + n] = reduce64(a1, m.q, m.mu_hi, m.mu_lo);
+  st4(out + (size_t)i * N + n, make_uint4(reduce64(a0[0], m.q, m.mu_hi, m.mu_lo), reduce64(a0[1], m.q, m.mu_hi, m.mu_lo),
+                                          reduce64(a0[2], m.q, m.mu_hi, m.mu_lo), reduce64(a0[3], m.q, m.mu_hi, m.mu_lo)));
+  st4(out + ((size_t)L + i) * N + n,
+      make_uint4(reduce64(a1[0], m.q, m.mu_hi, m.mu_lo), reduce64(a1[1], m.q, m.mu_hi, m.mu_lo),
+                 reduce64(a1[2], m.q, m.mu_hi, m.mu_lo), reduce64(a1[3], m.q, m.mu_hi, m.mu_lo)));
 }
 
 // Ciphertext sum: out = a + b over [2][L][N].
@@ -286,8 +297,9 @@ __global__ __launch_bounds__(kWG) void k_ct_add(DevTab T, const uint32_t* a, con
   const size_t N = (size_t)1 << T.logN;
   const int r = blockIdx.y;  // 0 .. 2L-1
   const uint32_t q = ldc(T.mod + (r % L)).q;
-  const size_t e = (size_t)r * N + (size_t)blockIdx.x * kWG + threadIdx.x;
-  out[e] = csub(a[e] + b[e], q);
+  const size_t e = (size_t)r * N + ((size_t)blockIdx.x * kWG + threadIdx.x) * 4;
+  const uint4 x = ld4(a + e), y = ld4(b + e);
+  st4(out + e, make_uint4(csub(x.x + y.x, q), csub(x.y + y.y, q), csub(x.z + y.z, q), csub(x.w + y.w, q)));
 }
 
 // ============================================================================
@@ -402,13 +414,13 @@ hipError_t launch_pmult_sum(const Ctx& c, const uint32_t* const* cts, const uint
     a.p[i] = cts[i];
     b.p[i] = pts[i];
   }
-  k_pmult_sum<<<dim3(c.N / kWG, L), kWG, 0, st>>>(c.tab(), a, b, nb, L, out);
+  k_pmult_sum<<<dim3(c.N / (4 * kWG), L), kWG, 0, st>>>(c.tab(), a, b, nb, L, out);
   return hipGetLastError();
 }
 
 hipError_t launch_ct_add(const Ctx& c, const uint32_t* a, const uint32_t* b, int L, uint32_t* out,
                          hipStream_t st) {
-  k_ct_add<<<dim3(c.N / kWG, 2 * L), kWG, 0, st>>>(c.tab(), a, b, L, out);
+  k_ct_add<<<dim3(c.N / (4 * kWG), 2 * L), kWG, 0, st>>>(c.tab(), a, b, L, out);
   return hipGetLastError();
 }
 
