@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--small-reps", type=int, default=10000,
@@ -149,6 +150,12 @@ def main():
     out_r = torch.empty((2, L, N), dtype=torch.int32, device="cuda")
     out_s = torch.empty((2, L - 1, N), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+
+    # kernel schedule picked by the library's autotuner (before any timing)
+    schedule = None
+    if not args.no_tune:
+        sched, sched_us = P.ckks_ctx_tune(h, L, 3, stream)
+        schedule = dict(sched, hmult_us=round(sched_us, 2))
 
     def step():
         P.ckks_hmult(h, d_ct1, d_ct2, L, d_rlk, out_m, ws, stream)
@@ -241,6 +248,7 @@ def main():
                              "p99": round(float(np.percentile(lat, 99)), 2),
                              "reps": int(len(lat))},
         "hmult_latency_us_n12_l4": small,
+        "schedule": schedule,
         "path": path,
         "batched": batched,
         "roofline": roofline,

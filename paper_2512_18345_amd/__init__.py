@@ -22,7 +22,8 @@ __all__ = [
     "ckks_batch_destroy", "ckks_batch_plan", "ckks_batch_get_plan", "ckks_batch_set_plan",
     "ckks_batch_tune", "ckks_batch_tune_log", "ckks_stats", "ckks_server_create", "ckks_server_submit",
     "ckks_server_poll", "ckks_server_drain", "ckks_server_stats", "ckks_server_times",
-    "ckks_server_destroy", "ckks_pmult_sum", "ckks_add",
+    "ckks_server_destroy", "ckks_pmult_sum", "ckks_add", "ckks_schedule", "ckks_ctx_get_schedule",
+    "ckks_ctx_set_schedule", "ckks_ctx_tune",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,6 +48,16 @@ class ckks_job(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("L", ctypes.c_int), ("rot", ctypes.c_int),
                 ("reserved", ctypes.c_int), ("in0", ctypes.c_void_p), ("in1", ctypes.c_void_p),
                 ("key", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class ckks_schedule(ctypes.Structure):
+    """Mirror of struct ckks_schedule (include/ckks.h)."""
+    _fields_ = [("bconv_up_rows", ctypes.c_int), ("bconv_down_rows", ctypes.c_int),
+                ("small_grid", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        return dict(bconv_up_rows=self.bconv_up_rows, bconv_down_rows=self.bconv_down_rows,
+                    small_grid=self.small_grid)
 
 
 class ckks_batch_plan(ctypes.Structure):
@@ -97,6 +108,9 @@ _SIGS = {
     "ckks_batch_launch": [_vp, _vp],
     "ckks_batch_destroy": [_vp],
     "ckks_batch_get_plan": [_vp, _vp],
+    "ckks_ctx_get_schedule": [_vp, _vp],
+    "ckks_ctx_set_schedule": [_vp, _vp],
+    "ckks_ctx_tune": [_vp, _i, _i, _vp, _vp, _vp],
     "ckks_batch_set_plan": [_vp, _vp],
     "ckks_batch_tune": [_vp, _i, _vp, _vp, _vp],
     "ckks_batch_tune_log": [_vp, _vp, _vp, _i, ctypes.POINTER(_i)],
@@ -283,6 +297,26 @@ def ckks_batch_get_plan(batch) -> dict:
 def ckks_batch_set_plan(batch, jobs_per_launch=0, streams=1, split=1):
     p = ckks_batch_plan(int(jobs_per_launch), int(streams), int(split), 0)
     _check(lib().ckks_batch_set_plan(batch, ctypes.cast(ctypes.byref(p), _vp)))
+
+
+def ckks_ctx_get_schedule(ctx) -> dict:
+    s = ckks_schedule()
+    _check(lib().ckks_ctx_get_schedule(ctx, ctypes.cast(ctypes.byref(s), _vp)))
+    return s.as_dict()
+
+
+def ckks_ctx_set_schedule(ctx, bconv_up_rows=12, bconv_down_rows=6, small_grid=128):
+    s = ckks_schedule(int(bconv_up_rows), int(bconv_down_rows), int(small_grid), 0)
+    _check(lib().ckks_ctx_set_schedule(ctx, ctypes.cast(ctypes.byref(s), _vp)))
+
+
+def ckks_ctx_tune(ctx, L, reps=3, stream=None):
+    """Autotune the context's kernel schedule at level L; returns (schedule dict, us per HMult)."""
+    s = ckks_schedule()
+    us = ctypes.c_float()
+    _check(lib().ckks_ctx_tune(ctx, int(L), int(reps), _stream(stream),
+                               ctypes.cast(ctypes.byref(s), _vp), ctypes.cast(ctypes.byref(us), _vp)))
+    return s.as_dict(), float(us.value)
 
 
 def ckks_batch_tune_log(batch) -> list:

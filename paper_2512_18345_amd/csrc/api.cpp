@@ -540,6 +540,104 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int L, uint32_t* out, 
   return CKKS_OK;
 }
 
+int ckks_ctx_get_schedule(const ckks_ctx* ctx, ckks_schedule* sched) {
+  if (!ctx || !sched) return fail(CKKS_EINVAL, "null argument");
+  const Ctx::Sched& s = ctx->c.sched;
+  *sched = ckks_schedule{s.up_rows, s.down_rows, s.small_grid, 0};
+  return CKKS_OK;
+}
+
+namespace {
+bool sched_ok(const ckks_schedule& s) {
+  auto rows_ok = [](int r) { return r == 4 || r == 6 || r == 12; };
+  return rows_ok(s.bconv_up_rows) && rows_ok(s.bconv_down_rows) && s.small_grid >= 0 &&
+         s.small_grid <= 65535;
+}
+}  // namespace
+
+int ckks_ctx_set_schedule(ckks_ctx* ctx, const ckks_schedule* sched) {
+  if (!ctx || !sched) return fail(CKKS_EINVAL, "null argument");
+  if (!sched_ok(*sched))
+    return fail(CKKS_EINVAL, "schedule needs rows in {4, 6, 12} and 0 <= small_grid <= 65535");
+  ctx->c.sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid};
+  return CKKS_OK;
+}
+
+int ckks_ctx_tune(ckks_ctx* ctx, int L, int reps, void* stream, ckks_schedule* best, float* best_us) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (reps < 1 || reps > 1000) return fail(CKKS_EINVAL, "need 1 <= reps <= 1000");
+  Ctx& c = ctx->c;
+  DeviceGuard g(c.device);
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t N = c.N;
+  const size_t ct_b = 2 * (size_t)L * N * 4;
+  const size_t key_b = (size_t)c.beta_max() * 2 * (c.L_max + c.k) * N * 4;
+  const size_t ws_b = round_up(ks_ws_words(c, L) * 4);
+  void *d_ct = nullptr, *d_key = nullptr, *d_out = nullptr, *d_ws = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  auto cleanup = [&]() {
+    if (d_ct) (void)hipFree(d_ct);
+    if (d_key) (void)hipFree(d_key);
+    if (d_out) (void)hipFree(d_out);
+    if (d_ws) (void)hipFree(d_ws);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  };
+  if (hipMalloc(&d_ct, 2 * ct_b) != hipSuccess || hipMalloc(&d_key, key_b) != hipSuccess ||
+      hipMalloc(&d_out, ct_b) != hipSuccess || hipMalloc(&d_ws, ws_b) != hipSuccess) {
+    cleanup();
+    return fail(CKKS_ENOMEM, "tuning buffers");
+  }
+  hipError_t e = hipMemsetAsync(d_ct, 0, 2 * ct_b, st);
+  if (e == hipSuccess) e = hipMemsetAsync(d_key, 0, key_b, st);
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  const Ctx::Sched start = c.sched;
+  Ctx::Sched top = start;
+  float top_us = -1.f;
+  const uint32_t* ct1 = (const uint32_t*)d_ct;
+  const uint32_t* ct2 = (const uint32_t*)((char*)d_ct + ct_b);
+  for (int up : {12, 6, 4}) {
+    for (int down : {6, 12, 4}) {
+      for (int small : {128, 0, 512}) {
+        if (e != hipSuccess) break;
+        c.sched = Ctx::Sched{up, down, small};
+        auto once = [&]() {
+          return run_one(c, KS_HMULT, L, 0, ct1, ct2, (const uint32_t*)d_key, (uint32_t*)d_out, d_ws, st);
+        };
+        if (once() != CKKS_OK) {
+          e = hipErrorUnknown;
+          break;
+        }
+        if ((e = hipEventRecord(t0, st)) != hipSuccess) break;
+        for (int r = 0; r < reps; ++r)
+          if (once() != CKKS_OK) {
+            e = hipErrorUnknown;
+            break;
+          }
+        if (e != hipSuccess || (e = hipEventRecord(t1, st)) != hipSuccess ||
+            (e = hipEventSynchronize(t1)) != hipSuccess)
+          break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+        const float us = 1e3f * ms / reps;
+        if (top_us < 0.f || us < top_us) {
+          top_us = us;
+          top = c.sched;
+        }
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  c.sched = e == hipSuccess ? top : start;
+  if (e != hipSuccess) return hip_fail(e, "timing candidate schedules");
+  if (best) *best = ckks_schedule{top.up_rows, top.down_rows, top.small_grid, 0};
+  if (best_us) *best_us = top_us;
+  return CKKS_OK;
+}
+
 int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int use_graph,
                       ckks_batch** out) {
   if (!ctx || !h_jobs || !out || n < 1 || n > 65535) return fail(CKKS_EINVAL, "bad batch arguments");

@@ -105,6 +105,15 @@ struct Ctx {
     int count = 0;
   };
   mutable Trace trace;
+
+  // Kernel schedule of the key-switching pipeline (ckks_ctx_set_schedule /
+  // ckks_ctx_tune): BConv output rows per work-group for ModUp and ModDown
+  // (4, 6 or 12), and the largest inner-product grid that uses one thread
+  // group per digit (0: never).  Results do not depend on it.
+  struct Sched {
+    int up_rows = 12, down_rows = 6, small_grid = 128;
+  };
+  Sched sched;
   // The start / stop events for the next launch of a traced stage (both null
   // when the stage is not traced or the capacity is used up).  Launchers pass
   // them to hipExtLaunchKernel, which records them at the dispatch's own

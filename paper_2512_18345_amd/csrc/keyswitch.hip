@@ -951,10 +951,17 @@ size_t ks_hoist_ws_words(const Ctx& c, int L) {
 size_t rs_ws_words(const Ctx& c, int L) { return (2 + 2 * (size_t)L) * c.N; }
 
 namespace {
-constexpr int kRB = 12;  // ModUp BConv output rows per work-group (inputs re-read once per group)
-constexpr int kRB7 = 6;
-// K5 grids up to this many work-groups use the one-group-per-digit variant.
-constexpr int kSmallGrid = 128;  // ModDown BConv: fewer rows per work-group, so that L = 36 still gives 768 of them
+// BConv output rows per work-group (Ctx::Sched): a group re-reads its
+// inputs once, so more rows per group mean fewer re-reads but fewer groups.
+template <template <int, int> class KERN, int A>
+void launch_bconv(const Ctx& c, int stage, int rows, dim3 g, hipStream_t st, const KsConst& K,
+                  const JobArg<KsJob>& J, int gr) {
+  switch (rows) {
+    case 4: klaunch(c, stage, KERN<A, 4>::fn, g, st, K, J, gr); break;
+    case 6: klaunch(c, stage, KERN<A, 6>::fn, g, st, K, J, gr); break;
+    default: klaunch(c, stage, KERN<A, 12>::fn, g, st, K, J, gr); break;
+  }
+}
 
 // Launch of a pipeline kernel; when its stage is traced, the trace events
 // are attached to the dispatch itself.
@@ -970,18 +977,26 @@ void klaunch(const Ctx& c, int stage, F kern, dim3 g, hipStream_t st, A... args)
 }
 
 // Dispatch a small compile-time count (digit size or special-prime count, 1..16).
+template <int A, int RB>
+struct K3fn {
+  static constexpr auto fn = k3_bconv_up<A, RB>;
+};
+template <int A, int RB>
+struct K7fn {
+  static constexpr auto fn = k7_bconv_down<A, RB>;
+};
 template <int A>
 struct K3 {
   static void run(const Ctx& c, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
                   int gr) {
-    klaunch(c, CKKS_STAGE_BCONV_UP, k3_bconv_up<A, kRB>, g, st, K, J, gr);
+    launch_bconv<K3fn, A>(c, CKKS_STAGE_BCONV_UP, c.sched.up_rows, g, st, K, J, gr);
   }
 };
 template <int A>
 struct K7 {
   static void run(const Ctx& c, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
                   int gr) {
-    klaunch(c, CKKS_STAGE_BCONV_DOWN, k7_bconv_down<A, kRB7>, g, st, K, J, gr);
+    launch_bconv<K7fn, A>(c, CKKS_STAGE_BCONV_DOWN, c.sched.down_rows, g, st, K, J, gr);
   }
 };
 
@@ -1006,8 +1021,10 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   const int tiles = c.N / kTile;
   const int cols = c.N / (4 * kWG);  // BConv: four coefficients per thread
   const int bmax = c.beta(Lmax);
-  const int up_groups = (Rmax + kRB - 1) / kRB;
-  const int down_groups = (Lmax + kRB7 - 1) / kRB7;
+  const int up_rows = c.sched.up_rows == 4 || c.sched.up_rows == 6 ? c.sched.up_rows : 12;
+  const int down_rows = c.sched.down_rows == 4 || c.sched.down_rows == 6 ? c.sched.down_rows : 12;
+  const int up_groups = (Rmax + up_rows - 1) / up_rows;
+  const int down_groups = (Lmax + down_rows - 1) / down_rows;
   hipError_t e;
   if (with_modup) {
     klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1>, dim3(tiles, Lmax, njobs), st, K, jobs);
@@ -1025,7 +1042,7 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   auto k5 = [&](int stage, int part, hipStream_t s5, int rows) {
     const dim3 g5(tiles, rows, njobs);
     const int nb = std::max(c.beta(Lmax), 2);  // slots for the launch's own largest digit count
-    if (tiles * rows * njobs <= kSmallGrid && nb <= 4) {  // too few work-groups to fill the CUs
+    if (tiles * rows * njobs <= c.sched.small_grid && nb <= 4) {  // too few work-groups to fill the CUs
       switch (nb) {
         case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2>, g5, kWGP, s5, K, jobs, part); break;
         case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3>, g5, kWGP, s5, K, jobs, part); break;

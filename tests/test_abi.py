@@ -60,7 +60,9 @@ def test_server_and_batch_argument_errors_without_a_device():
     with pytest.raises(P.CkksError):
         P.ckks_batch_create(None, [])
     for call in (lambda: P.ckks_batch_get_plan(None), lambda: P.ckks_batch_set_plan(None, 0, 1, 1),
-                 lambda: P.ckks_batch_tune(None, 3, stream=0), lambda: P.ckks_batch_tune_log(None)):
+                 lambda: P.ckks_batch_tune(None, 3, stream=0), lambda: P.ckks_batch_tune_log(None),
+                 lambda: P.ckks_ctx_get_schedule(None), lambda: P.ckks_ctx_set_schedule(None),
+                 lambda: P.ckks_ctx_tune(None, 4, stream=0)):
         with pytest.raises(P.CkksError) as e:
             call()
         assert e.value.code == -1

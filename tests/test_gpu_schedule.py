@@ -1,0 +1,58 @@
+"""Kernel schedules (BConv rows per work-group, the per-digit inner-product
+variant for small grids) change only the launch shapes: every schedule, and
+the one the autotuner picks, must give the oracle's results bit for bit."""
+import pytest
+import torch
+
+import ckks_inputs as ci
+import oracle as O
+import paper_2512_18345_amd as P
+from gpu_helpers import dev, empty, first_mismatch, host
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+SCHEDULES = [(12, 6, 128), (4, 4, 0), (6, 12, 512), (12, 12, 0), (4, 6, 65535)]
+
+
+@pytest.mark.parametrize("name,L", [("n16_l36", 36), ("n16_l36", 13), ("n12_l4", 4), ("toy_n12", 5)])
+def test_every_schedule_matches_the_oracle(name, L):
+    spec = ci.get(name)
+    par = O.Params.from_spec(spec)
+    ctx = P.Context.from_spec(spec)
+    h, N = ctx.handle, spec.N
+    rng = ci.Rng(spec.seed + 300)
+    ct1, ct2 = rng.polys(2, spec.q[:L], N), rng.polys(2, spec.q[:L], N)
+    key = rng.evk(spec)
+    rot = rng.rotation(N)
+    want_m = O.hmult(par, ct1, ct2, L, key)
+    want_r = O.hrot(par, ct1, L, rot, key)
+    d1, d2, dk = dev(ct1), dev(ct2), dev(key)
+    try:
+        for sch in SCHEDULES:
+            P.ckks_ctx_set_schedule(h, *sch)
+            assert P.ckks_ctx_get_schedule(h) == dict(zip(("bconv_up_rows", "bconv_down_rows", "small_grid"), sch))
+            out = empty(2, L, N)
+            P.ckks_hmult(h, d1, d2, L, dk, out, ctx.workspace("HMULT", L))
+            msg = first_mismatch(host(out), want_m)
+            assert not msg, f"schedule {sch} hmult: {msg}"
+            P.ckks_hrot(h, d1, L, rot, dk, out, ctx.workspace("HROT", L))
+            msg = first_mismatch(host(out), want_r)
+            assert not msg, f"schedule {sch} hrot: {msg}"
+        best, us = P.ckks_ctx_tune(h, L, reps=1)
+        assert us > 0 and best == P.ckks_ctx_get_schedule(h)
+        out = empty(2, L, N)
+        P.ckks_hmult(h, d1, d2, L, dk, out, ctx.workspace("HMULT", L))
+        msg = first_mismatch(host(out), want_m)
+        assert not msg, f"tuned schedule {best}: {msg}"
+    finally:
+        P.ckks_ctx_set_schedule(h, 12, 6, 128)
+
+
+def test_bad_schedules_are_rejected():
+    ctx = P.Context.from_spec(ci.get("n12_l4"))
+    for sch in [(5, 6, 128), (12, 8, 128), (12, 6, -1), (12, 6, 70000)]:
+        with pytest.raises(P.CkksError) as e:
+            P.ckks_ctx_set_schedule(ctx.handle, *sch)
+        assert e.value.code == -1
+    assert P.ckks_ctx_get_schedule(ctx.handle) == dict(bconv_up_rows=12, bconv_down_rows=6, small_grid=128)
