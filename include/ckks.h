@@ -228,9 +228,9 @@ int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, 
 /*
  * Kernel schedule of a context's key-switching pipeline (the limb-tile and
  * work-group shapes that do not change any result):
- *   bconv_up_rows    ModUp BConv output rows per work-group: 4, 6 or 12
+ *   bconv_up_rows    ModUp BConv output rows per work-group: 2, 4, 6 or 12
  *                    (a work-group re-reads its digit's inputs once)
- *   bconv_down_rows  ModDown BConv output rows per work-group: 4, 6 or 12
+ *   bconv_down_rows  ModDown BConv output rows per work-group: 2, 4, 6 or 12
  *   small_grid       inner-product launches of at most this many
  *                    work-groups use one thread group per digit tile
  *                    (0: never)
@@ -246,12 +246,12 @@ typedef struct ckks_schedule {
 } ckks_schedule;
 
 int ckks_ctx_get_schedule(const ckks_ctx *ctx, ckks_schedule *sched);
-/* Errors: CKKS_EINVAL for rows outside {4, 6, 12} or small_grid outside [0, 65535]. */
+/* Errors: CKKS_EINVAL for rows outside {2, 4, 6, 12} or small_grid outside [0, 65535]. */
 int ckks_ctx_set_schedule(ckks_ctx *ctx, const ckks_schedule *sched);
 /*
  * Schedule autotuner: times an HMult at level L on synthetic inputs (zeros;
  * the arithmetic is data-independent) under every candidate schedule
- * (rows in {4, 6, 12} for both BConvs, small_grid in {0, 128, 512}), one
+ * (rows in {2, 4, 6, 12} for both BConvs, small_grid in {0, 128, 1024}), one
  * warm-up and `reps` calls each between two events on `stream`, and keeps
  * the fastest.  Allocates its own device buffers (inputs, key, workspace)
  * for the duration of the call and synchronises `stream`; not for use while

@@ -549,7 +549,7 @@ int ckks_ctx_get_schedule(const ckks_ctx* ctx, ckks_schedule* sched) {
 
 namespace {
 bool sched_ok(const ckks_schedule& s) {
-  auto rows_ok = [](int r) { return r == 4 || r == 6 || r == 12; };
+  auto rows_ok = [](int r) { return r == 2 || r == 4 || r == 6 || r == 12; };
   return rows_ok(s.bconv_up_rows) && rows_ok(s.bconv_down_rows) && s.small_grid >= 0 &&
          s.small_grid <= 65535;
 }
@@ -558,7 +558,7 @@ bool sched_ok(const ckks_schedule& s) {
 int ckks_ctx_set_schedule(ckks_ctx* ctx, const ckks_schedule* sched) {
   if (!ctx || !sched) return fail(CKKS_EINVAL, "null argument");
   if (!sched_ok(*sched))
-    return fail(CKKS_EINVAL, "schedule needs rows in {4, 6, 12} and 0 <= small_grid <= 65535");
+    return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12} and 0 <= small_grid <= 65535");
   ctx->c.sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid};
   return CKKS_OK;
 }
@@ -598,9 +598,9 @@ int ckks_ctx_tune(ckks_ctx* ctx, int L, int reps, void* stream, ckks_schedule* b
   float top_us = -1.f;
   const uint32_t* ct1 = (const uint32_t*)d_ct;
   const uint32_t* ct2 = (const uint32_t*)((char*)d_ct + ct_b);
-  for (int up : {12, 6, 4}) {
-    for (int down : {6, 12, 4}) {
-      for (int small : {128, 0, 512}) {
+  for (int up : {12, 6, 4, 2}) {
+    for (int down : {6, 12, 4, 2}) {
+      for (int small : {128, 0, 1024}) {
         if (e != hipSuccess) break;
         c.sched = Ctx::Sched{up, down, small};
         auto once = [&]() {

@@ -108,7 +108,7 @@ struct Ctx {
 
   // Kernel schedule of the key-switching pipeline (ckks_ctx_set_schedule /
   // ckks_ctx_tune): BConv output rows per work-group for ModUp and ModDown
-  // (4, 6 or 12), and the largest inner-product grid that uses one thread
+  // (2, 4, 6 or 12), and the largest inner-product grid that uses one thread
   // group per digit (0: never).  Results do not depend on it.
   struct Sched {
     int up_rows = 12, down_rows = 6, small_grid = 128;

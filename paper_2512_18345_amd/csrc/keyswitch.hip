@@ -957,6 +957,7 @@ template <template <int, int> class KERN, int A>
 void launch_bconv(const Ctx& c, int stage, int rows, dim3 g, hipStream_t st, const KsConst& K,
                   const JobArg<KsJob>& J, int gr) {
   switch (rows) {
+    case 2: klaunch(c, stage, KERN<A, 2>::fn, g, st, K, J, gr); break;
     case 4: klaunch(c, stage, KERN<A, 4>::fn, g, st, K, J, gr); break;
     case 6: klaunch(c, stage, KERN<A, 6>::fn, g, st, K, J, gr); break;
     default: klaunch(c, stage, KERN<A, 12>::fn, g, st, K, J, gr); break;
@@ -1021,8 +1022,8 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   const int tiles = c.N / kTile;
   const int cols = c.N / (4 * kWG);  // BConv: four coefficients per thread
   const int bmax = c.beta(Lmax);
-  const int up_rows = c.sched.up_rows == 4 || c.sched.up_rows == 6 ? c.sched.up_rows : 12;
-  const int down_rows = c.sched.down_rows == 4 || c.sched.down_rows == 6 ? c.sched.down_rows : 12;
+  auto rows_of = [](int r) { return r == 2 || r == 4 || r == 6 ? r : 12; };
+  const int up_rows = rows_of(c.sched.up_rows), down_rows = rows_of(c.sched.down_rows);
   const int up_groups = (Rmax + up_rows - 1) / up_rows;
   const int down_groups = (Lmax + down_rows - 1) / down_rows;
   hipError_t e;

@@ -12,7 +12,7 @@ from gpu_helpers import dev, empty, first_mismatch, host
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
-SCHEDULES = [(12, 6, 128), (4, 4, 0), (6, 12, 512), (12, 12, 0), (4, 6, 65535)]
+SCHEDULES = [(12, 6, 128), (4, 4, 0), (6, 12, 512), (2, 2, 0), (4, 6, 65535), (2, 12, 1024)]
 
 
 @pytest.mark.parametrize("name,L", [("n16_l36", 36), ("n16_l36", 13), ("n12_l4", 4), ("toy_n12", 5)])
@@ -51,7 +51,7 @@ def test_every_schedule_matches_the_oracle(name, L):
 
 def test_bad_schedules_are_rejected():
     ctx = P.Context.from_spec(ci.get("n12_l4"))
-    for sch in [(5, 6, 128), (12, 8, 128), (12, 6, -1), (12, 6, 70000)]:
+    for sch in [(5, 6, 128), (12, 8, 128), (1, 6, 128), (12, 6, -1), (12, 6, 70000)]:
         with pytest.raises(P.CkksError) as e:
             P.ckks_ctx_set_schedule(ctx.handle, *sch)
         assert e.value.code == -1
