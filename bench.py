@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
+    ap.add_argument("--schedule", type=str, default="", metavar="UP,DOWN,SMALL",
+                    help="run under this kernel schedule instead of the autotuned one")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--small-reps", type=int, default=10000,
@@ -153,7 +155,10 @@ def main():
 
     # kernel schedule picked by the library's autotuner (before any timing)
     schedule = None
-    if not args.no_tune:
+    if args.schedule:
+        P.ckks_ctx_set_schedule(h, *[int(v) for v in args.schedule.split(",")])
+        schedule = dict(P.ckks_ctx_get_schedule(h), fixed=True)
+    elif not args.no_tune:
         sched, sched_us = P.ckks_ctx_tune(h, L, 3, stream)
         schedule = dict(sched, hmult_us=round(sched_us, 2))
 
