@@ -520,15 +520,21 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   }
 }
 
-// K5 for small grids (few tiles x rows, e.g. N = 2^12): one 1024-thread
-// work-group per (tile, row).  Thread group d = threadIdx.x / 256 stages and
-// transforms digit tile d, so the digits' transforms run side by side; then
-// every thread forms the inner product of one quad over all digits.  Every
-// barrier below is reached by all threads of the work-group.
-constexpr int kWGP = 4 * kWG;
-template <int LOGN1, int NB>
-__global__ __launch_bounds__(kWGP) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob> JA, int part) {
+// K5 for small grids (few tiles x rows, e.g. N = 2^12): one work-group per
+// (tile, row) of BPW blocks (16: a whole 4096-word tile, 1024 threads; 4: a
+// quarter tile, 256 threads, four times the work-groups for the same rows).
+// Thread group d = threadIdx.x / (16 BPW) stages and transforms digit tile d,
+// so the digits' transforms run side by side; then every thread forms the
+// inner product of one quad over all digits.  Every barrier below is reached
+// by all threads of the work-group.  The slots keep the full tile stride, so
+// the twiddle table fits the pads of slots 0 and 1 for either BPW.
+template <int BPW>
+constexpr int k5p_threads() { return 4 * 16 * BPW; }
+template <int LOGN1, int NB, int BPW>
+__global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob> JA, int part) {
   static_assert(NB >= 2 && NB <= 4, "one thread group per digit tile");
+  static_assert(BPW == 4 || BPW == 16, "a quarter or a whole tile");
+  constexpr int GS = 16 * BPW;  // threads per digit group: 16 elements each
   const KsJob J = JA.get(blockIdx.z);
   const int logN = K.T.logN;
   const size_t N = (size_t)1 << logN;
@@ -539,10 +545,10 @@ __global__ __launch_bounds__(kWGP) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob>
   const int pi = ks_pidx(r, V.L, K.T.L_max);
   const ModC m = ldc(K.T.mod + pi);
   const uint32_t q = m.q, q2 = 2 * q;
-  const int blk0 = blockIdx.x * 16;
+  const int blk0 = blockIdx.x * BPW;
   const uint32_t base = blk0 * 256;
   const size_t KR = (size_t)K.T.L_max + K.k;  // key rows
-  const int grp = threadIdx.x / kWG, lt = threadIdx.x % kWG;
+  const int grp = threadIdx.x / GS, lt = threadIdx.x % GS;
   // digit this thread group owns, and whether its tile needs the transform
   const int lo = grp * K.alpha, hi = min(lo + K.alpha, V.L);
   const bool have = grp < NB && grp < V.beta;
@@ -553,21 +559,21 @@ __global__ __launch_bounds__(kWGP) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob>
     if (own) {
       const uint32_t* drow = (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(drow + (lt + kk * kWG) * 4);
+      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(drow + (lt + kk * GS) * 4);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) lds_blk4_store(slot, (lt + kk * kWG) * 4, v[kk]);
+      for (int kk = 0; kk < 4; ++kk) lds_blk4_store(slot, (lt + kk * GS) * 4, v[kk]);
     } else {
       const uint32_t* zrow = V.z + ((size_t)grp * V.R + r) * N + base;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(zrow + (lt + kk * kWG) * 4);
+      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(zrow + (lt + kk * GS) * 4);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const int e = (lt + kk * kWG) * 4;
+        const int e = (lt + kk * GS) * 4;
         lds_blk4_store(slot, e, twist4(v[kk], K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
       }
     }
   }
-  if (grp == 0) stage_tw_pads(s, K.T.blk_tw(pi), lt);
+  if (threadIdx.x < 256) stage_tw_pads(s, K.T.blk_tw(pi), threadIdx.x);
   // key words of this thread's quad, requested before the transforms
   const int e = threadIdx.x * 4;
   uint4 k0v[NB], k1v[NB];
@@ -620,7 +626,7 @@ __global__ __launch_bounds__(kWGP) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob>
   __syncthreads();
   lds_blk4_store(s, e, res0);
   lds_blk4_store(s + kLds, e, res1);
-  if (grp == 0) stage_tw_pads(s, K.T.blk_itw(pi), lt);
+  if (threadIdx.x < 256) stage_tw_pads(s, K.T.blk_itw(pi), threadIdx.x);
   __syncthreads();
   if (grp < 2) blk_phase<4, true>(s + grp * kLds, 0, PadTw{s}, q, q2, lt);
   __syncthreads();
@@ -630,7 +636,7 @@ __global__ __launch_bounds__(kWGP) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob>
     uint32_t* dst = grp ? acc1 : acc0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int ee = (lt + kk * kWG) * 4;
+      const int ee = (lt + kk * GS) * 4;
       st4(dst + ee, twist4(lds_blk4(s + grp * kLds, ee), K.T.blk_itwist(pi, blk0 + (ee >> 8)), ee & 255, q));
     }
   }
@@ -1044,10 +1050,22 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     const dim3 g5(tiles, rows, njobs);
     const int nb = std::max(c.beta(Lmax), 2);  // slots for the launch's own largest digit count
     if (tiles * rows * njobs <= c.sched.small_grid && nb <= 4) {  // too few work-groups to fill the CUs
+      // quarter tiles while four times the work-groups still fit one per CU
+      if (4 * tiles * rows * njobs <= 256) {
+        const dim3 g4(4 * tiles, rows, njobs);
+        constexpr int T4 = k5p_threads<4>();
+        switch (nb) {
+          case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2, 4>, g4, T4, s5, K, jobs, part); break;
+          case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3, 4>, g4, T4, s5, K, jobs, part); break;
+          default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4, 4>, g4, T4, s5, K, jobs, part); break;
+        }
+        return;
+      }
+      constexpr int T16 = k5p_threads<16>();
       switch (nb) {
-        case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2>, g5, kWGP, s5, K, jobs, part); break;
-        case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3>, g5, kWGP, s5, K, jobs, part); break;
-        default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4>, g5, kWGP, s5, K, jobs, part); break;
+        case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2, 16>, g5, T16, s5, K, jobs, part); break;
+        case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3, 16>, g5, T16, s5, K, jobs, part); break;
+        default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4, 16>, g5, T16, s5, K, jobs, part); break;
       }
       return;
     }
