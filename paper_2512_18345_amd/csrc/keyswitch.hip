@@ -161,26 +161,26 @@ __global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA)
   }
 }
 
-template <int LOGN1>
+template <int LOGN1, int CW>
 __global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const int r = blockIdx.y;
   if (J.kind == KS_HOIST || r >= J.L) return;
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
-  constexpr int C = ColGeom<LOGN1>::C;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW>::LDS];
+  constexpr int C = ColGeom<LOGN1, CW>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + r).q, q2 = 2 * q;
-  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, K.T.col_itw(r), ColGeom<LOGN1>::N1);
+  __shared__ uint2 stw[ColGeom<LOGN1, CW>::N1];
+  stage_tw(stw, K.T.col_itw(r), ColGeom<LOGN1, CW>::N1);
   const uint2 sc = ldc(K.modup_scale + (size_t)J.L * K.T.L_max + r);
   const int col0 = blockIdx.x * C;
   uint32_t* row = ks_view(J, K, N).y + (size_t)r * N;
-  load_cols<LOGN1>(s, row, col0);
+  load_cols<LOGN1, CW>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, stw, q, q2);
+  col_stages<LOGN1, true, CW>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1, CW>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, c = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
@@ -647,27 +647,27 @@ __global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K,
 // ============================================================================
 
 // INTT column pass of the P rows (already through the block pass) -> x [2][k].
-template <int LOGN1>
+template <int LOGN1, int CW>
 __global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const size_t N = (size_t)1 << K.T.logN;
   const KsView V = ks_view(J, K, N);
   const int c = blockIdx.y / K.k, mm = blockIdx.y % K.k;
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
-  constexpr int C = ColGeom<LOGN1>::C;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW>::LDS];
+  constexpr int C = ColGeom<LOGN1, CW>::C;
   const int pi = K.T.L_max + mm;
-  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1>::N1);
+  __shared__ uint2 stw[ColGeom<LOGN1, CW>::N1];
+  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
   const uint2 sc = ldc(K.moddown_scale + mm);
   const int col0 = blockIdx.x * C;
-  load_cols<LOGN1>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
+  load_cols<LOGN1, CW>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, stw, q, q2);
+  col_stages<LOGN1, true, CW>(s, stw, q, q2);
   __syncthreads();
   uint32_t* row = V.x + ((size_t)c * K.k + mm) * N;
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1, CW>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
@@ -839,25 +839,25 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
   }
 }
 
-template <int LOGN1>
+template <int LOGN1, int CW>
 __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, pi = J.L - 1;
-  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1>::N1);
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
-  constexpr int C = ColGeom<LOGN1>::C;
+  __shared__ uint2 stw[ColGeom<LOGN1, CW>::N1];
+  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW>::N1);
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW>::LDS];
+  constexpr int C = ColGeom<LOGN1, CW>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const ModC m = ldc(K.T.mod + pi);
   const uint32_t q = m.q, q2 = 2 * q;
   const int col0 = blockIdx.x * C;
   uint32_t* row = J.ws + (size_t)c * N;
-  load_cols<LOGN1>(s, row, col0);
+  load_cols<LOGN1, CW>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true>(s, stw, q, q2);
+  col_stages<LOGN1, true, CW>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1, CW>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * kWG) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
@@ -1021,6 +1021,13 @@ hipError_t small_dispatch(int v, const Ctx& c, dim3 g, hipStream_t st, const KsC
   }
 }
 
+// Column passes with fewer work-groups than this (half a work-group per CU)
+// use the narrowest column tiles, which double the work-groups at N = 2^16:
+// for such a grid every CU that joins shortens the pass (the rescale's INTT
+// of one limb: 8.4 -> 5.5 us), while at 192 or 288 work-groups the half-line
+// row segments cost more than the extra CUs gain (K2: 12.1 -> 14.1 us).
+constexpr int kNarrowBelow = 128;
+
 template <int L1>
 hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs, int njobs,
                        int Lmax, bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp) {
@@ -1035,8 +1042,12 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   hipError_t e;
   if (with_modup) {
     klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1>, dim3(tiles, Lmax, njobs), st, K, jobs);
-    klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1>, dim3(ColGeom<L1>::TILES, Lmax, njobs), st, K,
-            jobs);
+    if (ColGeom<L1>::TILES * Lmax * njobs < kNarrowBelow)
+      klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, kColNarrow<L1>>,
+              dim3(ColGeom<L1, kColNarrow<L1>>::TILES, Lmax, njobs), st, K, jobs);
+    else
+      klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, 0>, dim3(ColGeom<L1>::TILES, Lmax, njobs), st, K,
+              jobs);
     e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
     if (e != hipSuccess) return e;
     klaunch(c, CKKS_STAGE_NTT_COLS_UP, k4_ntt_cols<L1>, dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), st,
@@ -1104,8 +1115,12 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     if (with_hoist) k5h(CKKS_STAGE_NTT_IP, KS_PART_ALL, st, Rmax);
   }
   if (split && (e = hipEventRecord(sp.join, sp.side)) != hipSuccess) return e;
-  klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1>, dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), st,
-          K, jobs);
+  if (ColGeom<L1>::TILES * 2 * c.k * njobs < kNarrowBelow)
+    klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, kColNarrow<L1>>,
+            dim3(ColGeom<L1, kColNarrow<L1>>::TILES, 2 * c.k, njobs), st, K, jobs);
+  else
+    klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, 0>, dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), st,
+            K, jobs);
   e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
   if (e != hipSuccess) return e;
   klaunch(c, CKKS_STAGE_NTT_COLS_DOWN, k8_ntt_cols_w<L1>, dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), st,
@@ -1120,7 +1135,10 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
                        int Lmax, hipStream_t st) {
   const int tiles = c.N / kTile;
   r1_intt_blks<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
-  r2_intt_cols<L1><<<dim3(ColGeom<L1>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
+  if (ColGeom<L1>::TILES * 2 * njobs < kNarrowBelow)
+    r2_intt_cols<L1, kColNarrow<L1>><<<dim3(ColGeom<L1, kColNarrow<L1>>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
+  else
+    r2_intt_cols<L1, 0><<<dim3(ColGeom<L1>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
   r3_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
   klaunch(c, CKKS_STAGE_RESCALE_NTT, r4_ntt_blks_combine<L1>, dim3(tiles, 2 * (Lmax - 1), njobs), st, K,
           jobs);

@@ -18,18 +18,23 @@ namespace ckks {
 
 constexpr int kLds = 4352;  // padded block-pass tile: 16 x (256 + 16) words
 
-// Column-pass tile for N1 = 2^LOGN1 rows: C adjacent columns, at least 32 so
-// that every row segment is a whole 128-byte line (narrower tiles fetch each
-// line twice).
-template <int LOGN1>
+// Column-pass tile for N1 = 2^LOGN1 rows: C adjacent columns, by default at
+// least 32 so that every row segment is a whole 128-byte line (narrower tiles
+// fetch each line twice).  CW != 0 asks for CW columns instead (at least
+// kTile / N1, so that every thread still holds 16 elements): the narrowest,
+// kColNarrow, doubles the work-groups of a launch at N = 2^16.
+template <int LOGN1, int CW = 0>
 struct ColGeom {
+  static_assert(CW == 0 || CW >= (kTile >> LOGN1), "at least 16 elements per thread");
   static constexpr int N1 = 1 << LOGN1;
-  static constexpr int C = (kTile >> LOGN1) < 32 ? 32 : (kTile >> LOGN1);
+  static constexpr int C = CW ? CW : (kTile >> LOGN1) < 32 ? 32 : (kTile >> LOGN1);
   static constexpr int ELEMS = C * N1;             // 4096 or 8192
   static constexpr int QUADS = ELEMS / (4 * kWG);  // 16-byte quads per thread in load/store
   static constexpr int LDS = ELEMS + N1;           // with the 16-word pad per 16 rows
   static constexpr int TILES = 256 / C;            // column tiles per limb
 };
+template <int LOGN1>
+constexpr int kColNarrow = kTile >> LOGN1;
 
 __device__ __forceinline__ int lidx_col(int pos, int c, int C) { return pos * C + c + ((pos >> 4) << 4); }
 __device__ __forceinline__ int lidx_blk(int line, int pos) { return line * 272 + pos + (pos >> 4); }
@@ -167,9 +172,9 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, ui
 }
 
 // All column stages of one tile, forward (high bits first) or inverse (low bits first).
-template <int LOGN1, bool INV>
+template <int LOGN1, bool INV, int CW = 0>
 __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
-  using G = ColGeom<LOGN1>;
+  using G = ColGeom<LOGN1, CW>;
   constexpr int REM = LOGN1 - 4;  // 0..4
   if (!INV) {
     col_phase<4, false, G::ELEMS>(s, LOGN1, G::C, REM, tw, q, q2);
@@ -216,9 +221,9 @@ __device__ __forceinline__ uint4 twist4(uint4 v, const uint2* __restrict__ tb, i
 
 // ----- tile load / store helpers --------------------------------------------
 // Thread t's k-th quad of a column tile: tile-linear word 4 (t + 256 k) = (pos, c).
-template <int LOGN1>
+template <int LOGN1, int CW = 0>
 __device__ __forceinline__ void col_quad(int k, int& pos, int& c) {
-  using G = ColGeom<LOGN1>;
+  using G = ColGeom<LOGN1, CW>;
   const int lin = (threadIdx.x + k * kWG) * 4;
   pos = lin / G::C;
   c = lin & (G::C - 1);
@@ -231,25 +236,25 @@ __device__ __forceinline__ void stage_tw(uint2* stw, const uint2* __restrict__ t
   if ((int)threadIdx.x < n) stw[threadIdx.x] = tw[threadIdx.x];
 }
 
-template <int LOGN1>
+template <int LOGN1, int CW = 0>
 __device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restrict__ row, int col0) {
-  using G = ColGeom<LOGN1>;
+  using G = ColGeom<LOGN1, CW>;
 #pragma unroll
   for (int k = 0; k < G::QUADS; ++k) {
     int pos, c;
-    col_quad<LOGN1>(k, pos, c);
+    col_quad<LOGN1, CW>(k, pos, c);
     const uint4 v = ld4(row + pos * 256 + col0 + c);
     *reinterpret_cast<uint4*>(s + lidx_col(pos, c, G::C)) = v;
   }
 }
 
-template <int LOGN1>
+template <int LOGN1, int CW = 0>
 __device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restrict__ row, int col0) {
-  using G = ColGeom<LOGN1>;
+  using G = ColGeom<LOGN1, CW>;
 #pragma unroll
   for (int k = 0; k < G::QUADS; ++k) {
     int pos, c;
-    col_quad<LOGN1>(k, pos, c);
+    col_quad<LOGN1, CW>(k, pos, c);
     st4(row + pos * 256 + col0 + c, *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, G::C)));
   }
 }
