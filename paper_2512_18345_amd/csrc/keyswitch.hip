@@ -161,27 +161,27 @@ __global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA)
   }
 }
 
-template <int LOGN1, int CW>
-__global__ __launch_bounds__(kWG) void k2_intt_cols(KsConst K, JobArg<KsJob> JA) {
+template <int LOGN1, int CW, int T>
+__global__ __launch_bounds__(T) void k2_intt_cols(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const int r = blockIdx.y;
   if (J.kind == KS_HOIST || r >= J.L) return;
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW>::LDS];
-  constexpr int C = ColGeom<LOGN1, CW>::C;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
+  constexpr int C = ColGeom<LOGN1, CW, T>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + r).q, q2 = 2 * q;
-  __shared__ uint2 stw[ColGeom<LOGN1, CW>::N1];
-  stage_tw(stw, K.T.col_itw(r), ColGeom<LOGN1, CW>::N1);
+  __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
+  stage_tw(stw, K.T.col_itw(r), ColGeom<LOGN1, CW, T>::N1);
   const uint2 sc = ldc(K.modup_scale + (size_t)J.L * K.T.L_max + r);
   const int col0 = blockIdx.x * C;
   uint32_t* row = ks_view(J, K, N).y + (size_t)r * N;
-  load_cols<LOGN1, CW>(s, row, col0);
+  load_cols<LOGN1, CW, T>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true, CW>(s, stw, q, q2);
+  col_stages<LOGN1, true, CW, T>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1, CW>::QUADS; ++kk) {
-    const int lin = (threadIdx.x + kk * kWG) * 4;
+  for (int kk = 0; kk < ColGeom<LOGN1, CW, T>::QUADS; ++kk) {
+    const int lin = (threadIdx.x + kk * T) * 4;
     const int pos = lin / C, c = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, C));
     v.x = csub(mul_shoup(v.x, sc.x, sc.y, q), q);
@@ -647,28 +647,28 @@ __global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K,
 // ============================================================================
 
 // INTT column pass of the P rows (already through the block pass) -> x [2][k].
-template <int LOGN1, int CW>
-__global__ __launch_bounds__(kWG) void k6_intt_cols_p(KsConst K, JobArg<KsJob> JA) {
+template <int LOGN1, int CW, int T>
+__global__ __launch_bounds__(T) void k6_intt_cols_p(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const size_t N = (size_t)1 << K.T.logN;
   const KsView V = ks_view(J, K, N);
   const int c = blockIdx.y / K.k, mm = blockIdx.y % K.k;
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW>::LDS];
-  constexpr int C = ColGeom<LOGN1, CW>::C;
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
+  constexpr int C = ColGeom<LOGN1, CW, T>::C;
   const int pi = K.T.L_max + mm;
-  __shared__ uint2 stw[ColGeom<LOGN1, CW>::N1];
-  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW>::N1);
+  __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
+  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW, T>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
   const uint2 sc = ldc(K.moddown_scale + mm);
   const int col0 = blockIdx.x * C;
-  load_cols<LOGN1, CW>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
+  load_cols<LOGN1, CW, T>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
   __syncthreads();
-  col_stages<LOGN1, true, CW>(s, stw, q, q2);
+  col_stages<LOGN1, true, CW, T>(s, stw, q, q2);
   __syncthreads();
   uint32_t* row = V.x + ((size_t)c * K.k + mm) * N;
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1, CW>::QUADS; ++kk) {
-    const int lin = (threadIdx.x + kk * kWG) * 4;
+  for (int kk = 0; kk < ColGeom<LOGN1, CW, T>::QUADS; ++kk) {
+    const int lin = (threadIdx.x + kk * T) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
     v.x = csub(mul_shoup(v.x, sc.x, sc.y, q), q);
@@ -1027,6 +1027,11 @@ hipError_t small_dispatch(int v, const Ctx& c, dim3 g, hipStream_t st, const KsC
 // of one limb: 8.4 -> 5.5 us), while at 192 or 288 work-groups the half-line
 // row segments cost more than the extra CUs gain (K2: 12.1 -> 14.1 us).
 constexpr int kNarrowBelow = 128;
+// Threads of the INTT column passes K2 and K6 over whole-line tiles: 16
+// elements per thread (512 threads for the 8192-word tiles at N = 2^16), two
+// waves per SIMD for launches of about one work-group per CU.
+template <int L1>
+constexpr int kColThreads = ColGeom<L1>::ELEMS / 16;
 
 template <int L1>
 hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs, int njobs,
@@ -1043,11 +1048,11 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   if (with_modup) {
     klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1>, dim3(tiles, Lmax, njobs), st, K, jobs);
     if (ColGeom<L1>::TILES * Lmax * njobs < kNarrowBelow)
-      klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, kColNarrow<L1>>,
+      klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, kColNarrow<L1>, kWG>,
               dim3(ColGeom<L1, kColNarrow<L1>>::TILES, Lmax, njobs), st, K, jobs);
     else
-      klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, 0>, dim3(ColGeom<L1>::TILES, Lmax, njobs), st, K,
-              jobs);
+      klaunch_b(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, 0, kColThreads<L1>>,
+                dim3(ColGeom<L1>::TILES, Lmax, njobs), kColThreads<L1>, st, K, jobs);
     e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
     if (e != hipSuccess) return e;
     klaunch(c, CKKS_STAGE_NTT_COLS_UP, k4_ntt_cols<L1>, dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), st,
@@ -1116,11 +1121,11 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   }
   if (split && (e = hipEventRecord(sp.join, sp.side)) != hipSuccess) return e;
   if (ColGeom<L1>::TILES * 2 * c.k * njobs < kNarrowBelow)
-    klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, kColNarrow<L1>>,
+    klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, kColNarrow<L1>, kWG>,
             dim3(ColGeom<L1, kColNarrow<L1>>::TILES, 2 * c.k, njobs), st, K, jobs);
   else
-    klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, 0>, dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), st,
-            K, jobs);
+    klaunch_b(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, 0, kColThreads<L1>>,
+              dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), kColThreads<L1>, st, K, jobs);
   e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
   if (e != hipSuccess) return e;
   klaunch(c, CKKS_STAGE_NTT_COLS_DOWN, k8_ntt_cols_w<L1>, dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), st,

@@ -22,14 +22,17 @@ constexpr int kLds = 4352;  // padded block-pass tile: 16 x (256 + 16) words
 // least 32 so that every row segment is a whole 128-byte line (narrower tiles
 // fetch each line twice).  CW != 0 asks for CW columns instead (at least
 // kTile / N1, so that every thread still holds 16 elements): the narrowest,
-// kColNarrow, doubles the work-groups of a launch at N = 2^16.
-template <int LOGN1, int CW = 0>
+// kColNarrow, doubles the work-groups of a launch at N = 2^16.  T threads
+// share a tile (kWG, or more for a tile of more than 4096 elements, down to 16
+// elements per thread).
+template <int LOGN1, int CW = 0, int T = kWG>
 struct ColGeom {
   static_assert(CW == 0 || CW >= (kTile >> LOGN1), "at least 16 elements per thread");
   static constexpr int N1 = 1 << LOGN1;
   static constexpr int C = CW ? CW : (kTile >> LOGN1) < 32 ? 32 : (kTile >> LOGN1);
   static constexpr int ELEMS = C * N1;             // 4096 or 8192
-  static constexpr int QUADS = ELEMS / (4 * kWG);  // 16-byte quads per thread in load/store
+  static_assert(ELEMS >= 16 * T, "at least 16 elements per thread");
+  static constexpr int QUADS = ELEMS / (4 * T);    // 16-byte quads per thread in load/store
   static constexpr int LDS = ELEMS + N1;           // with the 16-word pad per 16 rows
   static constexpr int TILES = 256 / C;            // column tiles per limb
 };
@@ -64,14 +67,14 @@ __device__ __forceinline__ void stage_tw_pads(uint32_t* s, const uint2* __restri
 }
 
 // ----- column-pass phases (stages on pos bits [blo, blo + LOGR)) -----------
-template <int LOGR, bool INV, int ELEMS>
+template <int LOGR, bool INV, int ELEMS, int T = kWG>
 __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo,
                                           const uint2* __restrict__ tw, uint32_t q, uint32_t q2) {
   constexpr int R = 1 << LOGR;
-  constexpr int GPT = ELEMS / R / kWG;
+  constexpr int GPT = ELEMS / R / T;
 #pragma unroll
   for (int gg = 0; gg < GPT; ++gg) {
-    const int g = threadIdx.x + gg * kWG;
+    const int g = threadIdx.x + gg * T;
     const int c = g & (C - 1);
     const int rest = g / C;
     const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
@@ -172,21 +175,21 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, ui
 }
 
 // All column stages of one tile, forward (high bits first) or inverse (low bits first).
-template <int LOGN1, bool INV, int CW = 0>
+template <int LOGN1, bool INV, int CW = 0, int T = kWG>
 __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
-  using G = ColGeom<LOGN1, CW>;
+  using G = ColGeom<LOGN1, CW, T>;
   constexpr int REM = LOGN1 - 4;  // 0..4
   if (!INV) {
-    col_phase<4, false, G::ELEMS>(s, LOGN1, G::C, REM, tw, q, q2);
+    col_phase<4, false, G::ELEMS, T>(s, LOGN1, G::C, REM, tw, q, q2);
     if constexpr (REM > 0) {
       __syncthreads();
-      col_phase<(REM > 0 ? REM : 1), false, G::ELEMS>(s, LOGN1, G::C, 0, tw, q, q2);
+      col_phase<(REM > 0 ? REM : 1), false, G::ELEMS, T>(s, LOGN1, G::C, 0, tw, q, q2);
     }
   } else {
-    col_phase<4, true, G::ELEMS>(s, LOGN1, G::C, 0, tw, q, q2);
+    col_phase<4, true, G::ELEMS, T>(s, LOGN1, G::C, 0, tw, q, q2);
     if constexpr (REM > 0) {
       __syncthreads();
-      col_phase<(REM > 0 ? REM : 1), true, G::ELEMS>(s, LOGN1, G::C, 4, tw, q, q2);
+      col_phase<(REM > 0 ? REM : 1), true, G::ELEMS, T>(s, LOGN1, G::C, 4, tw, q, q2);
     }
   }
 }
@@ -221,10 +224,10 @@ __device__ __forceinline__ uint4 twist4(uint4 v, const uint2* __restrict__ tb, i
 
 // ----- tile load / store helpers --------------------------------------------
 // Thread t's k-th quad of a column tile: tile-linear word 4 (t + 256 k) = (pos, c).
-template <int LOGN1, int CW = 0>
+template <int LOGN1, int CW = 0, int T = kWG>
 __device__ __forceinline__ void col_quad(int k, int& pos, int& c) {
-  using G = ColGeom<LOGN1, CW>;
-  const int lin = (threadIdx.x + k * kWG) * 4;
+  using G = ColGeom<LOGN1, CW, T>;
+  const int lin = (threadIdx.x + k * T) * 4;
   pos = lin / G::C;
   c = lin & (G::C - 1);
 }
@@ -236,25 +239,25 @@ __device__ __forceinline__ void stage_tw(uint2* stw, const uint2* __restrict__ t
   if ((int)threadIdx.x < n) stw[threadIdx.x] = tw[threadIdx.x];
 }
 
-template <int LOGN1, int CW = 0>
+template <int LOGN1, int CW = 0, int T = kWG>
 __device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restrict__ row, int col0) {
-  using G = ColGeom<LOGN1, CW>;
+  using G = ColGeom<LOGN1, CW, T>;
 #pragma unroll
   for (int k = 0; k < G::QUADS; ++k) {
     int pos, c;
-    col_quad<LOGN1, CW>(k, pos, c);
+    col_quad<LOGN1, CW, T>(k, pos, c);
     const uint4 v = ld4(row + pos * 256 + col0 + c);
     *reinterpret_cast<uint4*>(s + lidx_col(pos, c, G::C)) = v;
   }
 }
 
-template <int LOGN1, int CW = 0>
+template <int LOGN1, int CW = 0, int T = kWG>
 __device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restrict__ row, int col0) {
-  using G = ColGeom<LOGN1, CW>;
+  using G = ColGeom<LOGN1, CW, T>;
 #pragma unroll
   for (int k = 0; k < G::QUADS; ++k) {
     int pos, c;
-    col_quad<LOGN1, CW>(k, pos, c);
+    col_quad<LOGN1, CW, T>(k, pos, c);
     st4(row + pos * 256 + col0 + c, *reinterpret_cast<const uint4*>(s + lidx_col(pos, c, G::C)));
   }
 }
