@@ -229,8 +229,8 @@ __global__ __launch_bounds__(kWG) void k3_bconv_up(KsConst K, JobArg<KsJob> JA, 
   }
 }
 
-template <int LOGN1>
-__global__ __launch_bounds__(kWG) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) {
+template <int LOGN1, int T>
+__global__ __launch_bounds__(T) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   if (J.kind == KS_HOIST) return;
   const size_t N = (size_t)1 << K.T.logN;
@@ -240,18 +240,18 @@ __global__ __launch_bounds__(kWG) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) 
   if (j >= V.beta) return;
   const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
   if (r >= lo && r < hi) return;
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, 0, T>::LDS];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
-  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, K.T.col_tw(pi), ColGeom<LOGN1>::N1);
+  __shared__ uint2 stw[ColGeom<LOGN1, 0, T>::N1];
+  stage_tw(stw, K.T.col_tw(pi), ColGeom<LOGN1, 0, T>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
-  const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
+  const int col0 = blockIdx.x * ColGeom<LOGN1, 0, T>::C;
   uint32_t* row = V.z + (size_t)gr * N;
-  load_cols<LOGN1>(s, row, col0);
+  load_cols<LOGN1, 0, T>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, stw, q, q2);
+  col_stages<LOGN1, false, 0, T>(s, stw, q, q2);
   __syncthreads();
-  store_cols<LOGN1>(s, row, col0);
+  store_cols<LOGN1, 0, T>(s, row, col0);
 }
 
 // ============================================================================
@@ -710,25 +710,25 @@ __global__ __launch_bounds__(kWG) void k7_bconv_down(KsConst K, JobArg<KsJob> JA
   }
 }
 
-template <int LOGN1>
-__global__ __launch_bounds__(kWG) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA) {
+template <int LOGN1, int T>
+__global__ __launch_bounds__(T) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const size_t N = (size_t)1 << K.T.logN;
   const KsView V = ks_view(J, K, N);
   const int gr = blockIdx.y;
   if (gr >= 2 * V.L) return;
   const int i = gr % V.L;
-  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1>::N1);
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
+  __shared__ uint2 stw[ColGeom<LOGN1, 0, T>::N1];
+  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, 0, T>::N1);
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, 0, T>::LDS];
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
-  const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
+  const int col0 = blockIdx.x * ColGeom<LOGN1, 0, T>::C;
   uint32_t* row = V.w + (size_t)gr * N;
-  load_cols<LOGN1>(s, row, col0);
+  load_cols<LOGN1, 0, T>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false>(s, stw, q, q2);
+  col_stages<LOGN1, false, 0, T>(s, stw, q, q2);
   __syncthreads();
-  store_cols<LOGN1>(s, row, col0);
+  store_cols<LOGN1, 0, T>(s, row, col0);
 }
 
 // out[c][i] = (acc[c][i] - NTT(w)[c][i]) P^-1 (+ the job's epilogue term).
@@ -870,25 +870,25 @@ __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA)
 }
 
 // NTT column pass of t mod q_i for every i < L - 1 (the broadcast is the loader).
-template <int LOGN1>
-__global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) {
+template <int LOGN1, int T>
+__global__ __launch_bounds__(T) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int L1 = J.L - 1;
   const int gr = blockIdx.y;
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
-  __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1>::N1);
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1>::LDS];
-  constexpr int C = ColGeom<LOGN1>::C;
+  __shared__ uint2 stw[ColGeom<LOGN1, 0, T>::N1];
+  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, 0, T>::N1);
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, 0, T>::LDS];
+  constexpr int C = ColGeom<LOGN1, 0, T>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const ModC m = ldc(K.T.mod + i);
   const uint32_t q = m.q, q2 = 2 * q;
   const int col0 = blockIdx.x * C;
   const uint32_t* t = J.ws + (size_t)c * N;
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1>::QUADS; ++kk) {
-    const int lin = (threadIdx.x + kk * kWG) * 4;
+  for (int kk = 0; kk < ColGeom<LOGN1, 0, T>::QUADS; ++kk) {
+    const int lin = (threadIdx.x + kk * T) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = ld4(t + pos * 256 + col0 + cc);
     v.x = reduce32(v.x, q, m.mu32);
@@ -898,9 +898,9 @@ __global__ __launch_bounds__(kWG) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) 
     *reinterpret_cast<uint4*>(s + lidx_col(pos, cc, C)) = v;
   }
   __syncthreads();
-  col_stages<LOGN1, false>(s, stw, q, q2);
+  col_stages<LOGN1, false, 0, T>(s, stw, q, q2);
   __syncthreads();
-  store_cols<LOGN1>(s, J.ws + (size_t)(2 + gr) * N, col0);
+  store_cols<LOGN1, 0, T>(s, J.ws + (size_t)(2 + gr) * N, col0);
 }
 
 template <int LOGN1>
@@ -1027,9 +1027,9 @@ hipError_t small_dispatch(int v, const Ctx& c, dim3 g, hipStream_t st, const KsC
 // of one limb: 8.4 -> 5.5 us), while at 192 or 288 work-groups the half-line
 // row segments cost more than the extra CUs gain (K2: 12.1 -> 14.1 us).
 constexpr int kNarrowBelow = 128;
-// Threads of the INTT column passes K2 and K6 over whole-line tiles: 16
-// elements per thread (512 threads for the 8192-word tiles at N = 2^16), two
-// waves per SIMD for launches of about one work-group per CU.
+// Threads of the column passes over whole-line tiles: 16 elements per thread
+// (512 threads for the 8192-word tiles at N = 2^16; K2 and K6, launches of
+// about one work-group per CU, then run two waves per SIMD).
 template <int L1>
 constexpr int kColThreads = ColGeom<L1>::ELEMS / 16;
 
@@ -1055,8 +1055,8 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
                 dim3(ColGeom<L1>::TILES, Lmax, njobs), kColThreads<L1>, st, K, jobs);
     e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
     if (e != hipSuccess) return e;
-    klaunch(c, CKKS_STAGE_NTT_COLS_UP, k4_ntt_cols<L1>, dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), st,
-            K, jobs);
+    klaunch_b(c, CKKS_STAGE_NTT_COLS_UP, k4_ntt_cols<L1, kColThreads<L1>>,
+              dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), kColThreads<L1>, st, K, jobs);
   }
   // Stage 2.  With a side stream, complementary pipelining (Sec. IV-B): the
   // inner product of the P rows runs on st and ModDown's P-row chain (K6..K8,
@@ -1128,8 +1128,8 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
               dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), kColThreads<L1>, st, K, jobs);
   e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
   if (e != hipSuccess) return e;
-  klaunch(c, CKKS_STAGE_NTT_COLS_DOWN, k8_ntt_cols_w<L1>, dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), st,
-          K, jobs);
+  klaunch_b(c, CKKS_STAGE_NTT_COLS_DOWN, k8_ntt_cols_w<L1, kColThreads<L1>>,
+            dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), kColThreads<L1>, st, K, jobs);
   if (split && (e = hipStreamWaitEvent(st, sp.join, 0)) != hipSuccess) return e;
   klaunch(c, CKKS_STAGE_NTT_COMBINE, k9_ntt_blks_combine<L1>, dim3(tiles, 2 * Lmax, njobs), st, K, jobs);
   return hipGetLastError();
@@ -1144,7 +1144,7 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
     r2_intt_cols<L1, kColNarrow<L1>><<<dim3(ColGeom<L1, kColNarrow<L1>>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
   else
     r2_intt_cols<L1, 0><<<dim3(ColGeom<L1>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
-  r3_ntt_cols<L1><<<dim3(ColGeom<L1>::TILES, 2 * (Lmax - 1), njobs), kWG, 0, st>>>(K, jobs);
+  r3_ntt_cols<L1, kColThreads<L1>><<<dim3(ColGeom<L1>::TILES, 2 * (Lmax - 1), njobs), kColThreads<L1>, 0, st>>>(K, jobs);
   klaunch(c, CKKS_STAGE_RESCALE_NTT, r4_ntt_blks_combine<L1>, dim3(tiles, 2 * (Lmax - 1), njobs), st, K,
           jobs);
   return hipGetLastError();
