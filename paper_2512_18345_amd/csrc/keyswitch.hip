@@ -450,6 +450,10 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   // inner product, one quad at a time (one reduction per output, Sec. III-C2).
   // No branch on the digit count: tiles past beta (never staged) are masked
   // to zero, so the prefetched key words are consumed in straight-line code.
+  // The transformed words enter uncorrected: each lies in [0, 4q) and each
+  // key word below q < 2^30, so a product is below 2^62 and the sum of at
+  // most four (NB <= 4) stays below 2^64 for the single exact reduction.
+  static_assert(NB <= 4, "64-bit sum of lazy products");
   uint4 res0[4], res1[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -458,7 +462,7 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const uint32_t msk = j < V.beta ? ~0u : 0u;
-      uint4 v = canon4(lds_blk4(s + j * kLds, e), q, q2);
+      uint4 v = lds_blk4(s + j * kLds, e);
       v.x &= msk;
       v.y &= msk;
       v.z &= msk;
@@ -590,12 +594,14 @@ __global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K,
   if (have && !own) blk_phase<4, false>(s + grp * kLds, 0, tw, q, q2, lt);
   __syncthreads();
 
-  // inner product of quad e over the digits (one reduction per output)
+  // inner product of quad e over the digits (one reduction per output); the
+  // lazy words in [0, 4q) enter uncorrected, as in k5s (NB <= 4 products of
+  // at most 2^62 each)
   uint64_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) {
     const uint32_t msk = jj < V.beta ? ~0u : 0u;
-    uint4 v = canon4(lds_blk4(s + jj * kLds, e), q, q2);
+    uint4 v = lds_blk4(s + jj * kLds, e);
     v.x &= msk;
     v.y &= msk;
     v.z &= msk;
