@@ -88,33 +88,34 @@ __device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const ModC& m
   return reduce64((uint64_t)a * b, m.q, m.mu_hi, m.mu_lo);
 }
 
-// The four quads (words base + blk_elem(kk) .. +3) of row r of the polynomial
+// The QPT quads (words base + blk_elem(kk) .. +3) of row r of the polynomial
 // a job key-switches: d (PLAIN), c1 c1' (HMULT), sigma(c1) (HROT / HOIST).
 // Every load of a quad is issued before any of them is used.
+template <int QPT = 4>
 __device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, size_t N, int logN,
-                                         const ModC& m, uint4 d[4]) {
+                                         const ModC& m, uint4 d[QPT]) {
   if (J.kind == KS_PLAIN) {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) d[kk] = ld4(J.a + (size_t)r * N + base + blk_elem(kk));
+    for (int kk = 0; kk < QPT; ++kk) d[kk] = ld4(J.a + (size_t)r * N + base + blk_elem(kk));
     return;
   }
   const size_t row1 = (size_t)(J.L + r) * N;
   if (J.kind == KS_HMULT) {
-    uint4 x[4], y[4];
+    uint4 x[QPT], y[QPT];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int kk = 0; kk < QPT; ++kk) {
       x[kk] = ld4(J.a + row1 + base + blk_elem(kk));
       y[kk] = ld4(J.b + row1 + base + blk_elem(kk));
     }
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+    for (int kk = 0; kk < QPT; ++kk)
       d[kk] = make_uint4(mulmod(x[kk].x, y[kk].x, m), mulmod(x[kk].y, y[kk].y, m),
                          mulmod(x[kk].z, y[kk].z, m), mulmod(x[kk].w, y[kk].w, m));
     return;
   }
   const uint32_t* src = J.a + row1;
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const uint32_t n = base + blk_elem(kk);
     d[kk] = make_uint4(ld1(src + auto_src(n, J.gal, logN)), ld1(src + auto_src(n + 1, J.gal, logN)),
                        ld1(src + auto_src(n + 2, J.gal, logN)), ld1(src + auto_src(n + 3, J.gal, logN)));
@@ -125,7 +126,9 @@ __device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, s
 // Stage 1: ModUp
 // ============================================================================
 
-template <int LOGN1>
+// BPW blocks per work-group: 16 (a 4096-word tile, radix-16 phases) or, for
+// small grids, 4 (a quarter tile, one quad per thread, radix-4 phases).
+template <int LOGN1, int BPW>
 __global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const int r = blockIdx.y;
@@ -137,25 +140,29 @@ __global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA)
   const uint32_t q = m.q, q2 = 2 * q;
   __shared__ uint2 stw[256];
   stage_tw(stw, K.T.blk_itw(r), 256);
-  const int blk0 = blockIdx.x * 16;
+  constexpr int QPT = BPW / 4;  // quads per thread
+  const int blk0 = blockIdx.x * BPW;
   const uint32_t base = blk0 * 256;
   const KsView V = ks_view(J, K, N);
   uint32_t* de = V.de + (size_t)r * N + base;
   // all loads first: a store to de could alias the next quad's source
-  uint4 d[4];
-  load_d16(J, r, base, N, logN, m, d);
+  uint4 d[QPT];
+  load_d16<QPT>(J, r, base, N, logN, m, d);
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
     lds_blk4_store(s, e, d[kk]);
     if (J.kind != KS_PLAIN) st4(de + e, d[kk]);
   }
   __syncthreads();
-  blk_stages<true>(s, stw, q, q2);
+  if constexpr (BPW == 16)
+    blk_stages<true>(s, stw, q, q2);
+  else
+    blk_stages_r4<true, const uint2*, kWG>(s, stw, q, q2);
   __syncthreads();
   uint32_t* y = V.y + (size_t)r * N + base;
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
     st4(y + e, twist4(lds_blk4(s, e), K.T.blk_itwist(r, blk0 + (e >> 8)), e & 255, q));
   }
@@ -738,7 +745,8 @@ __global__ __launch_bounds__(T) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA) 
 }
 
 // out[c][i] = (acc[c][i] - NTT(w)[c][i]) P^-1 (+ the job's epilogue term).
-template <int LOGN1>
+// BPW blocks per work-group as in K1.
+template <int LOGN1, int BPW>
 __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const int logN = K.T.logN;
@@ -752,17 +760,21 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
   __shared__ __align__(16) uint32_t s[kLds];
   const ModC m = ldc(K.T.mod + i);
   const uint32_t q = m.q, q2 = 2 * q;
-  const int blk0 = blockIdx.x * 16;
+  constexpr int QPT = BPW / 4;  // quads per thread
+  const int blk0 = blockIdx.x * BPW;
   const uint32_t base = blk0 * 256;
   const uint32_t* wrow = V.w + (size_t)gr * N + base;
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
     lds_blk4_store(s, e, twist4(ld4(wrow + e),
                                 K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, stw, q, q2);
+  if constexpr (BPW == 16)
+    blk_stages<false>(s, stw, q, q2);
+  else
+    blk_stages_r4<false, const uint2*, kWG>(s, stw, q, q2);
   __syncthreads();
   const uint2 pv = ldc(K.pinv + i);
   const uint32_t* accr = V.acc + ((size_t)c * V.R + i) * N + base;
@@ -775,9 +787,9 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
   // (HMULT, formed here from the inputs), sigma(c0) (rotations, c = 0), else 0.
   // The term is formed as soon as its words arrive, so at most one quad's
   // inputs are live at a time.
-  uint4 av[4], dv[4];
+  uint4 av[QPT], dv[QPT];
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
     const uint32_t n = base + e;
     av[kk] = ld4(accr + e);
@@ -802,7 +814,7 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
     }
   }
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
     const uint4 w = canon4(lds_blk4(s, e), q, q2);
     const uint4 a = av[kk], d = dv[kk];
@@ -1052,7 +1064,10 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   const int down_groups = (Lmax + down_rows - 1) / down_rows;
   hipError_t e;
   if (with_modup) {
-    klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1>, dim3(tiles, Lmax, njobs), st, K, jobs);
+    if (4 * tiles * Lmax * njobs <= 256)  // quarter tiles still one work-group per CU
+      klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 4>, dim3(4 * tiles, Lmax, njobs), st, K, jobs);
+    else
+      klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16>, dim3(tiles, Lmax, njobs), st, K, jobs);
     if (ColGeom<L1>::TILES * Lmax * njobs < kNarrowBelow)
       klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, kColNarrow<L1>, kWG>,
               dim3(ColGeom<L1, kColNarrow<L1>>::TILES, Lmax, njobs), st, K, jobs);
@@ -1137,7 +1152,11 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   klaunch_b(c, CKKS_STAGE_NTT_COLS_DOWN, k8_ntt_cols_w<L1, kColThreads<L1>>,
             dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), kColThreads<L1>, st, K, jobs);
   if (split && (e = hipStreamWaitEvent(st, sp.join, 0)) != hipSuccess) return e;
-  klaunch(c, CKKS_STAGE_NTT_COMBINE, k9_ntt_blks_combine<L1>, dim3(tiles, 2 * Lmax, njobs), st, K, jobs);
+  if (4 * tiles * 2 * Lmax * njobs <= 256)
+    klaunch(c, CKKS_STAGE_NTT_COMBINE, k9_ntt_blks_combine<L1, 4>, dim3(4 * tiles, 2 * Lmax, njobs), st, K,
+            jobs);
+  else
+    klaunch(c, CKKS_STAGE_NTT_COMBINE, k9_ntt_blks_combine<L1, 16>, dim3(tiles, 2 * Lmax, njobs), st, K, jobs);
   return hipGetLastError();
 }
 

@@ -116,16 +116,18 @@ __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo
 // the pair on pos bit beta uses ctw[(1 << (7 - beta)) | (pos >> (beta + 1))],
 // and its stage on bit 7 (first forward / last inverse) multiplies by 1.
 // TW: a twiddle table indexable as tw[i] -> uint2 (a pointer, or PadTw below).
-// tid: the thread's index among the kWG threads that transform this tile.
-template <int LOGR, bool INV, class TW>
+// tid: the thread's index among the T threads that transform this tile, each
+// holding EPT elements (16 by default: kWG threads on 16 blocks).
+template <int LOGR, bool INV, class TW, int EPT = 16, int T = kWG>
 __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, uint32_t q,
                                           uint32_t q2, int tid = threadIdx.x) {
   constexpr int R = 1 << LOGR;
-  constexpr int GPT = 16 / R;
+  constexpr int GPT = EPT / R;
+  static_assert(GPT >= 1, "a group of R elements per thread at least");
   constexpr int NB = 8 - LOGR;
 #pragma unroll
   for (int gg = 0; gg < GPT; ++gg) {
-    const int g = tid + gg * kWG;
+    const int g = tid + gg * T;
     const int rest = g & ((1 << NB) - 1);
     const int line = g >> NB;
     const int base = ((rest >> blo) << (blo + LOGR)) | (rest & ((1 << blo) - 1));
@@ -191,6 +193,18 @@ __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_
       __syncthreads();
       col_phase<(REM > 0 ? REM : 1), true, G::ELEMS, T>(s, LOGN1, G::C, 4, tw, q, q2);
     }
+  }
+}
+
+// The eight block stages as four radix-4 phases, for tiles of T threads with
+// four elements each (small grids: a quarter as many butterflies per thread
+// as the radix-16 form, on four times the work-groups).
+template <bool INV, class TW, int T>
+__device__ __forceinline__ void blk_stages_r4(uint32_t* s, const TW& tw, uint32_t q, uint32_t q2) {
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (p) __syncthreads();
+    blk_phase<2, INV, TW, 4, T>(s, INV ? 2 * p : 6 - 2 * p, tw, q, q2);
   }
 }
 
