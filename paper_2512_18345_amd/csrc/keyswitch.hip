@@ -539,13 +539,17 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
 // inner product of one quad over all digits.  Every barrier below is reached
 // by all threads of the work-group.  The slots keep the full tile stride, so
 // the twiddle table fits the pads of slots 0 and 1 for either BPW.
-template <int BPW>
-constexpr int k5p_threads() { return 4 * 16 * BPW; }
-template <int LOGN1, int NB, int BPW>
-__global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob> JA, int part) {
+template <int BPW, int EPT>
+constexpr int k5p_threads() { return 4 * BPW * 256 / EPT; }
+template <int LOGN1, int NB, int BPW, int EPT>
+__global__ __launch_bounds__((k5p_threads<BPW, EPT>())) void k5p_ntt_blks_ip(KsConst K, JobArg<KsJob> JA,
+                                                                           int part) {
   static_assert(NB >= 2 && NB <= 4, "one thread group per digit tile");
-  static_assert(BPW == 4 || BPW == 16, "a quarter or a whole tile");
-  constexpr int GS = 16 * BPW;  // threads per digit group: 16 elements each
+  static_assert((EPT == 16 && (BPW == 4 || BPW == 16)) || (EPT == 4 && (BPW == 2 || BPW == 4)),
+                "radix-16 phases on 16 elements per thread, radix-4 phases on 4");
+  constexpr int GS = BPW * 256 / EPT;  // threads per digit group
+  constexpr int QPG = EPT / 4;         // quads per thread in a group's tile
+  constexpr int TQ = BPW * 64;         // quads of the tile: one per inner-product thread
   const KsJob J = JA.get(blockIdx.z);
   const int logN = K.T.logN;
   const size_t N = (size_t)1 << logN;
@@ -566,27 +570,29 @@ __global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K,
   const bool own = r >= lo && r < hi;
   if (have) {
     uint32_t* slot = s + grp * kLds;
-    uint4 v[4];
+    uint4 v[QPG];
     if (own) {
       const uint32_t* drow = (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(drow + (lt + kk * GS) * 4);
+      for (int kk = 0; kk < QPG; ++kk) v[kk] = ld4(drow + (lt + kk * GS) * 4);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) lds_blk4_store(slot, (lt + kk * GS) * 4, v[kk]);
+      for (int kk = 0; kk < QPG; ++kk) lds_blk4_store(slot, (lt + kk * GS) * 4, v[kk]);
     } else {
       const uint32_t* zrow = V.z + ((size_t)grp * V.R + r) * N + base;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) v[kk] = ld4(zrow + (lt + kk * GS) * 4);
+      for (int kk = 0; kk < QPG; ++kk) v[kk] = ld4(zrow + (lt + kk * GS) * 4);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
+      for (int kk = 0; kk < QPG; ++kk) {
         const int e = (lt + kk * GS) * 4;
         lds_blk4_store(slot, e, twist4(v[kk], K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
       }
     }
   }
   if (threadIdx.x < 256) stage_tw_pads(s, K.T.blk_tw(pi), threadIdx.x);
-  // key words of this thread's quad, requested before the transforms
-  const int e = threadIdx.x * 4;
+  // key words of this thread's quad, requested before the transforms (the
+  // first TQ threads form the inner product: all of them when EPT = 16)
+  const bool ipt = EPT == 16 || (int)threadIdx.x < TQ;
+  const int e = ipt ? threadIdx.x * 4 : 0;
   uint4 k0v[NB], k1v[NB];
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) {
@@ -596,9 +602,17 @@ __global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K,
   }
   __syncthreads();
   const PadTw tw{s};
-  if (have && !own) blk_phase<4, false>(s + grp * kLds, 4, tw, q, q2, lt);
-  __syncthreads();
-  if (have && !own) blk_phase<4, false>(s + grp * kLds, 0, tw, q, q2, lt);
+  if constexpr (EPT == 16) {
+    if (have && !own) blk_phase<4, false>(s + grp * kLds, 4, tw, q, q2, lt);
+    __syncthreads();
+    if (have && !own) blk_phase<4, false>(s + grp * kLds, 0, tw, q, q2, lt);
+  } else {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      if (p) __syncthreads();
+      if (have && !own) blk_phase<2, false, PadTw, 4, GS>(s + grp * kLds, 6 - 2 * p, tw, q, q2, lt);
+    }
+  }
   __syncthreads();
 
   // inner product of quad e over the digits (one reduction per output); the
@@ -629,26 +643,38 @@ __global__ __launch_bounds__(k5p_threads<BPW>()) void k5p_ntt_blks_ip(KsConst K,
   uint32_t* acc0 = V.acc + (size_t)r * N + base;
   uint32_t* acc1 = V.acc + ((size_t)V.R + r) * N + base;
   if (r < V.L) {  // uniform over the work-group
-    st4(acc0 + e, res0);
-    st4(acc1 + e, res1);
+    if (ipt) {
+      st4(acc0 + e, res0);
+      st4(acc1 + e, res1);
+    }
     return;
   }
   // P rows: the INTT block pass of ModDown, component c in slot c by thread
   // group c; inverse twiddles in the same pads (the forward ones were last
   // read before the previous barrier)
   __syncthreads();
-  lds_blk4_store(s, e, res0);
-  lds_blk4_store(s + kLds, e, res1);
+  if (ipt) {
+    lds_blk4_store(s, e, res0);
+    lds_blk4_store(s + kLds, e, res1);
+  }
   if (threadIdx.x < 256) stage_tw_pads(s, K.T.blk_itw(pi), threadIdx.x);
   __syncthreads();
-  if (grp < 2) blk_phase<4, true>(s + grp * kLds, 0, PadTw{s}, q, q2, lt);
-  __syncthreads();
-  if (grp < 2) blk_phase<4, true>(s + grp * kLds, 4, PadTw{s}, q, q2, lt);
+  if constexpr (EPT == 16) {
+    if (grp < 2) blk_phase<4, true>(s + grp * kLds, 0, PadTw{s}, q, q2, lt);
+    __syncthreads();
+    if (grp < 2) blk_phase<4, true>(s + grp * kLds, 4, PadTw{s}, q, q2, lt);
+  } else {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      if (p) __syncthreads();
+      if (grp < 2) blk_phase<2, true, PadTw, 4, GS>(s + grp * kLds, 2 * p, PadTw{s}, q, q2, lt);
+    }
+  }
   __syncthreads();
   if (grp < 2) {
     uint32_t* dst = grp ? acc1 : acc0;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int kk = 0; kk < QPG; ++kk) {
       const int ee = (lt + kk * GS) * 4;
       st4(dst + ee, twist4(lds_blk4(s + grp * kLds, ee), K.T.blk_itwist(pi, blk0 + (ee >> 8)), ee & 255, q));
     }
@@ -1087,22 +1113,33 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     const dim3 g5(tiles, rows, njobs);
     const int nb = std::max(c.beta(Lmax), 2);  // slots for the launch's own largest digit count
     if (tiles * rows * njobs <= c.sched.small_grid && nb <= 4) {  // too few work-groups to fill the CUs
-      // quarter tiles while four times the work-groups still fit one per CU
-      if (4 * tiles * rows * njobs <= 256) {
-        const dim3 g4(4 * tiles, rows, njobs);
-        constexpr int T4 = k5p_threads<4>();
+      // eighth tiles (radix-4 phases) while eight times the work-groups still
+      // fit one per CU, else quarter tiles while four times do
+      if (8 * tiles * rows * njobs <= 256) {
+        const dim3 g8(8 * tiles, rows, njobs);
+        constexpr int T8 = k5p_threads<2, 4>();
         switch (nb) {
-          case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2, 4>, g4, T4, s5, K, jobs, part); break;
-          case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3, 4>, g4, T4, s5, K, jobs, part); break;
-          default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4, 4>, g4, T4, s5, K, jobs, part); break;
+          case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2, 2, 4>, g8, T8, s5, K, jobs, part); break;
+          case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3, 2, 4>, g8, T8, s5, K, jobs, part); break;
+          default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4, 2, 4>, g8, T8, s5, K, jobs, part); break;
         }
         return;
       }
-      constexpr int T16 = k5p_threads<16>();
+      if (4 * tiles * rows * njobs <= 256) {
+        const dim3 g4(4 * tiles, rows, njobs);
+        constexpr int T4 = k5p_threads<4, 16>();
+        switch (nb) {
+          case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2, 4, 16>, g4, T4, s5, K, jobs, part); break;
+          case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3, 4, 16>, g4, T4, s5, K, jobs, part); break;
+          default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4, 4, 16>, g4, T4, s5, K, jobs, part); break;
+        }
+        return;
+      }
+      constexpr int T16 = k5p_threads<16, 16>();
       switch (nb) {
-        case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2, 16>, g5, T16, s5, K, jobs, part); break;
-        case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3, 16>, g5, T16, s5, K, jobs, part); break;
-        default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4, 16>, g5, T16, s5, K, jobs, part); break;
+        case 2: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 2, 16, 16>, g5, T16, s5, K, jobs, part); break;
+        case 3: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 3, 16, 16>, g5, T16, s5, K, jobs, part); break;
+        default: klaunch_b(c, stage, k5p_ntt_blks_ip<L1, 4, 16, 16>, g5, T16, s5, K, jobs, part); break;
       }
       return;
     }
