@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kWG) void k3_bconv_up(KsConst K, JobArg<KsJob> JA, 
   }
 }
 
-template <int LOGN1, int T>
+template <int LOGN1, int CW, int T>
 __global__ __launch_bounds__(T) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   if (J.kind == KS_HOIST) return;
@@ -247,18 +247,18 @@ __global__ __launch_bounds__(T) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) {
   if (j >= V.beta) return;
   const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
   if (r >= lo && r < hi) return;
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, 0, T>::LDS];
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
-  __shared__ uint2 stw[ColGeom<LOGN1, 0, T>::N1];
-  stage_tw(stw, K.T.col_tw(pi), ColGeom<LOGN1, 0, T>::N1);
+  __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
+  stage_tw(stw, K.T.col_tw(pi), ColGeom<LOGN1, CW, T>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
-  const int col0 = blockIdx.x * ColGeom<LOGN1, 0, T>::C;
+  const int col0 = blockIdx.x * ColGeom<LOGN1, CW, T>::C;
   uint32_t* row = V.z + (size_t)gr * N;
-  load_cols<LOGN1, 0, T>(s, row, col0);
+  load_cols<LOGN1, CW, T>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false, 0, T>(s, stw, q, q2);
+  col_stages<LOGN1, false, CW, T>(s, stw, q, q2);
   __syncthreads();
-  store_cols<LOGN1, 0, T>(s, row, col0);
+  store_cols<LOGN1, CW, T>(s, row, col0);
 }
 
 // ============================================================================
@@ -749,7 +749,7 @@ __global__ __launch_bounds__(kWG) void k7_bconv_down(KsConst K, JobArg<KsJob> JA
   }
 }
 
-template <int LOGN1, int T>
+template <int LOGN1, int CW, int T>
 __global__ __launch_bounds__(T) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const size_t N = (size_t)1 << K.T.logN;
@@ -757,17 +757,17 @@ __global__ __launch_bounds__(T) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA) 
   const int gr = blockIdx.y;
   if (gr >= 2 * V.L) return;
   const int i = gr % V.L;
-  __shared__ uint2 stw[ColGeom<LOGN1, 0, T>::N1];
-  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, 0, T>::N1);
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, 0, T>::LDS];
+  __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
+  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, CW, T>::N1);
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
-  const int col0 = blockIdx.x * ColGeom<LOGN1, 0, T>::C;
+  const int col0 = blockIdx.x * ColGeom<LOGN1, CW, T>::C;
   uint32_t* row = V.w + (size_t)gr * N;
-  load_cols<LOGN1, 0, T>(s, row, col0);
+  load_cols<LOGN1, CW, T>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, false, 0, T>(s, stw, q, q2);
+  col_stages<LOGN1, false, CW, T>(s, stw, q, q2);
   __syncthreads();
-  store_cols<LOGN1, 0, T>(s, row, col0);
+  store_cols<LOGN1, CW, T>(s, row, col0);
 }
 
 // out[c][i] = (acc[c][i] - NTT(w)[c][i]) P^-1 (+ the job's epilogue term).
@@ -883,26 +883,26 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
   }
 }
 
-template <int LOGN1, int CW>
-__global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
+template <int LOGN1, int CW, int T>
+__global__ __launch_bounds__(T) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, pi = J.L - 1;
-  __shared__ uint2 stw[ColGeom<LOGN1, CW>::N1];
-  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW>::N1);
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW>::LDS];
-  constexpr int C = ColGeom<LOGN1, CW>::C;
+  __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
+  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW, T>::N1);
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
+  constexpr int C = ColGeom<LOGN1, CW, T>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const ModC m = ldc(K.T.mod + pi);
   const uint32_t q = m.q, q2 = 2 * q;
   const int col0 = blockIdx.x * C;
   uint32_t* row = J.ws + (size_t)c * N;
-  load_cols<LOGN1, CW>(s, row, col0);
+  load_cols<LOGN1, CW, T>(s, row, col0);
   __syncthreads();
-  col_stages<LOGN1, true, CW>(s, stw, q, q2);
+  col_stages<LOGN1, true, CW, T>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1, CW>::QUADS; ++kk) {
-    const int lin = (threadIdx.x + kk * kWG) * 4;
+  for (int kk = 0; kk < ColGeom<LOGN1, CW, T>::QUADS; ++kk) {
+    const int lin = (threadIdx.x + kk * T) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = *reinterpret_cast<const uint4*>(s + lidx_col(pos, cc, C));
     v.x = csub(mul_shoup(v.x, m.ninv, m.ninv_s, q), q);
@@ -914,24 +914,24 @@ __global__ __launch_bounds__(kWG) void r2_intt_cols(KsConst K, JobArg<RsJob> JA)
 }
 
 // NTT column pass of t mod q_i for every i < L - 1 (the broadcast is the loader).
-template <int LOGN1, int T>
+template <int LOGN1, int CW, int T>
 __global__ __launch_bounds__(T) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int L1 = J.L - 1;
   const int gr = blockIdx.y;
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
-  __shared__ uint2 stw[ColGeom<LOGN1, 0, T>::N1];
-  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, 0, T>::N1);
-  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, 0, T>::LDS];
-  constexpr int C = ColGeom<LOGN1, 0, T>::C;
+  __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
+  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, CW, T>::N1);
+  __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
+  constexpr int C = ColGeom<LOGN1, CW, T>::C;
   const size_t N = (size_t)1 << K.T.logN;
   const ModC m = ldc(K.T.mod + i);
   const uint32_t q = m.q, q2 = 2 * q;
   const int col0 = blockIdx.x * C;
   const uint32_t* t = J.ws + (size_t)c * N;
 #pragma unroll
-  for (int kk = 0; kk < ColGeom<LOGN1, 0, T>::QUADS; ++kk) {
+  for (int kk = 0; kk < ColGeom<LOGN1, CW, T>::QUADS; ++kk) {
     const int lin = (threadIdx.x + kk * T) * 4;
     const int pos = lin / C, cc = lin & (C - 1);
     uint4 v = ld4(t + pos * 256 + col0 + cc);
@@ -942,9 +942,9 @@ __global__ __launch_bounds__(T) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) {
     *reinterpret_cast<uint4*>(s + lidx_col(pos, cc, C)) = v;
   }
   __syncthreads();
-  col_stages<LOGN1, false, 0, T>(s, stw, q, q2);
+  col_stages<LOGN1, false, CW, T>(s, stw, q, q2);
   __syncthreads();
-  store_cols<LOGN1, 0, T>(s, J.ws + (size_t)(2 + gr) * N, col0);
+  store_cols<LOGN1, CW, T>(s, J.ws + (size_t)(2 + gr) * N, col0);
 }
 
 template <int LOGN1>
@@ -1077,6 +1077,44 @@ constexpr int kNarrowBelow = 128;
 template <int L1>
 constexpr int kColThreads = ColGeom<L1>::ELEMS / 16;
 
+template <int L1, int CW, int T>
+struct K2c { static constexpr auto fn = k2_intt_cols<L1, CW, T>; };
+template <int L1, int CW, int T>
+struct K4c { static constexpr auto fn = k4_ntt_cols<L1, CW, T>; };
+template <int L1, int CW, int T>
+struct K6c { static constexpr auto fn = k6_intt_cols_p<L1, CW, T>; };
+template <int L1, int CW, int T>
+struct K8c { static constexpr auto fn = k8_ntt_cols_w<L1, CW, T>; };
+template <int L1, int CW, int T>
+struct R2c { static constexpr auto fn = r2_intt_cols<L1, CW, T>; };
+template <int L1, int CW, int T>
+struct R3c { static constexpr auto fn = r3_ntt_cols<L1, CW, T>; };
+
+// Launch a column pass over `rows` rows of every job in its tile shape:
+// quarter-width tiles in radix-4 phases (four elements per thread) when four
+// times the work-groups still fit one per CU and the quarter is at least 32
+// columns (N <= 2^13); the narrowest tiles under kNarrowBelow work-groups
+// where `narrow` allows; else whole-line tiles of 16 elements per thread.
+template <template <int, int, int> class KF, int L1, class JA>
+void col_launch(const Ctx& c, int stage, int rows, int njobs, bool narrow, hipStream_t st,
+                const KsConst& K, const JA& jobs) {
+  constexpr int TL = ColGeom<L1>::TILES;
+  if constexpr (ColGeom<L1>::C / 4 >= 32) {
+    if (4 * TL * rows * njobs <= 256) {
+      constexpr int CW = ColGeom<L1>::C / 4;
+      constexpr int T = CW * (1 << L1) / 4;
+      klaunch_b(c, stage, KF<L1, CW, T>::fn, dim3(4 * TL, rows, njobs), T, st, K, jobs);
+      return;
+    }
+  }
+  if (narrow && TL * rows * njobs < kNarrowBelow) {
+    klaunch(c, stage, KF<L1, kColNarrow<L1>, kWG>::fn, dim3(ColGeom<L1, kColNarrow<L1>>::TILES, rows, njobs),
+            st, K, jobs);
+    return;
+  }
+  klaunch_b(c, stage, KF<L1, 0, kColThreads<L1>>::fn, dim3(TL, rows, njobs), kColThreads<L1>, st, K, jobs);
+}
+
 template <int L1>
 hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs, int njobs,
                        int Lmax, bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp) {
@@ -1094,16 +1132,10 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
       klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 4>, dim3(4 * tiles, Lmax, njobs), st, K, jobs);
     else
       klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16>, dim3(tiles, Lmax, njobs), st, K, jobs);
-    if (ColGeom<L1>::TILES * Lmax * njobs < kNarrowBelow)
-      klaunch(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, kColNarrow<L1>, kWG>,
-              dim3(ColGeom<L1, kColNarrow<L1>>::TILES, Lmax, njobs), st, K, jobs);
-    else
-      klaunch_b(c, CKKS_STAGE_INTT_COLS, k2_intt_cols<L1, 0, kColThreads<L1>>,
-                dim3(ColGeom<L1>::TILES, Lmax, njobs), kColThreads<L1>, st, K, jobs);
+    col_launch<K2c, L1>(c, CKKS_STAGE_INTT_COLS, Lmax, njobs, true, st, K, jobs);
     e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
     if (e != hipSuccess) return e;
-    klaunch_b(c, CKKS_STAGE_NTT_COLS_UP, k4_ntt_cols<L1, kColThreads<L1>>,
-              dim3(ColGeom<L1>::TILES, bmax * Rmax, njobs), kColThreads<L1>, st, K, jobs);
+    col_launch<K4c, L1>(c, CKKS_STAGE_NTT_COLS_UP, bmax * Rmax, njobs, false, st, K, jobs);
   }
   // Stage 2.  With a side stream, complementary pipelining (Sec. IV-B): the
   // inner product of the P rows runs on st and ModDown's P-row chain (K6..K8,
@@ -1178,16 +1210,10 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     if (with_hoist) k5h(CKKS_STAGE_NTT_IP, KS_PART_ALL, st, Rmax);
   }
   if (split && (e = hipEventRecord(sp.join, sp.side)) != hipSuccess) return e;
-  if (ColGeom<L1>::TILES * 2 * c.k * njobs < kNarrowBelow)
-    klaunch(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, kColNarrow<L1>, kWG>,
-            dim3(ColGeom<L1, kColNarrow<L1>>::TILES, 2 * c.k, njobs), st, K, jobs);
-  else
-    klaunch_b(c, CKKS_STAGE_INTT_COLS_P, k6_intt_cols_p<L1, 0, kColThreads<L1>>,
-              dim3(ColGeom<L1>::TILES, 2 * c.k, njobs), kColThreads<L1>, st, K, jobs);
+  col_launch<K6c, L1>(c, CKKS_STAGE_INTT_COLS_P, 2 * c.k, njobs, true, st, K, jobs);
   e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
   if (e != hipSuccess) return e;
-  klaunch_b(c, CKKS_STAGE_NTT_COLS_DOWN, k8_ntt_cols_w<L1, kColThreads<L1>>,
-            dim3(ColGeom<L1>::TILES, 2 * Lmax, njobs), kColThreads<L1>, st, K, jobs);
+  col_launch<K8c, L1>(c, CKKS_STAGE_NTT_COLS_DOWN, 2 * Lmax, njobs, false, st, K, jobs);
   if (split && (e = hipStreamWaitEvent(st, sp.join, 0)) != hipSuccess) return e;
   if (4 * tiles * 2 * Lmax * njobs <= 256)
     klaunch(c, CKKS_STAGE_NTT_COMBINE, k9_ntt_blks_combine<L1, 4>, dim3(4 * tiles, 2 * Lmax, njobs), st, K,
@@ -1202,11 +1228,8 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
                        int Lmax, hipStream_t st) {
   const int tiles = c.N / kTile;
   r1_intt_blks<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
-  if (ColGeom<L1>::TILES * 2 * njobs < kNarrowBelow)
-    r2_intt_cols<L1, kColNarrow<L1>><<<dim3(ColGeom<L1, kColNarrow<L1>>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
-  else
-    r2_intt_cols<L1, 0><<<dim3(ColGeom<L1>::TILES, 2, njobs), kWG, 0, st>>>(K, jobs);
-  r3_ntt_cols<L1, kColThreads<L1>><<<dim3(ColGeom<L1>::TILES, 2 * (Lmax - 1), njobs), kColThreads<L1>, 0, st>>>(K, jobs);
+  col_launch<R2c, L1>(c, -1, 2, njobs, true, st, K, jobs);
+  col_launch<R3c, L1>(c, -1, 2 * (Lmax - 1), njobs, false, st, K, jobs);
   klaunch(c, CKKS_STAGE_RESCALE_NTT, r4_ntt_blks_combine<L1>, dim3(tiles, 2 * (Lmax - 1), njobs), st, K,
           jobs);
   return hipGetLastError();

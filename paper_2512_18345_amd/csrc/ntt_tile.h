@@ -21,17 +21,18 @@ constexpr int kLds = 4352;  // padded block-pass tile: 16 x (256 + 16) words
 // Column-pass tile for N1 = 2^LOGN1 rows: C adjacent columns, by default at
 // least 32 so that every row segment is a whole 128-byte line (narrower tiles
 // fetch each line twice).  CW != 0 asks for CW columns instead (at least
-// kTile / N1, so that every thread still holds 16 elements): the narrowest,
-// kColNarrow, doubles the work-groups of a launch at N = 2^16.  T threads
-// share a tile (kWG, or more for a tile of more than 4096 elements, down to 16
-// elements per thread).
+// kTile / N1 for 16 elements per thread): the narrowest, kColNarrow, doubles
+// the work-groups of a launch at N = 2^16.  T threads share a tile, EPT
+// elements each: a multiple of 16 (radix-16 phases), or 4 (radix-4 phases:
+// small grids, quarter-width tiles).
 template <int LOGN1, int CW = 0, int T = kWG>
 struct ColGeom {
-  static_assert(CW == 0 || CW >= (kTile >> LOGN1), "at least 16 elements per thread");
+  static_assert(CW == 0 || CW >= 16, "row segments of at least 64 bytes");
   static constexpr int N1 = 1 << LOGN1;
   static constexpr int C = CW ? CW : (kTile >> LOGN1) < 32 ? 32 : (kTile >> LOGN1);
-  static constexpr int ELEMS = C * N1;             // 4096 or 8192
-  static_assert(ELEMS >= 16 * T, "at least 16 elements per thread");
+  static constexpr int ELEMS = C * N1;             // 4096 or 8192 (fewer in quarter tiles)
+  static constexpr int EPT = ELEMS / T;            // elements per thread
+  static_assert(EPT % 16 == 0 || EPT == 4, "groups of 16 elements per thread, or 4 in radix-4 phases");
   static constexpr int QUADS = ELEMS / (4 * T);    // 16-byte quads per thread in load/store
   static constexpr int LDS = ELEMS + N1;           // with the 16-word pad per 16 rows
   static constexpr int TILES = 256 / C;            // column tiles per limb
@@ -180,6 +181,22 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, ui
 template <int LOGN1, bool INV, int CW = 0, int T = kWG>
 __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
   using G = ColGeom<LOGN1, CW, T>;
+  if constexpr (G::EPT == 4) {
+    // radix-4 phases (two bits each), a radix-2 phase for an odd log2 N1
+    constexpr int P4 = LOGN1 / 2, ODD = LOGN1 & 1;
+#pragma unroll
+    for (int p = 0; p < P4 + ODD; ++p) {
+      if (p) __syncthreads();
+      if (!INV) {
+        if (p < P4) col_phase<2, false, G::ELEMS, T>(s, LOGN1, G::C, LOGN1 - 2 - 2 * p, tw, q, q2);
+        else col_phase<1, false, G::ELEMS, T>(s, LOGN1, G::C, 0, tw, q, q2);
+      } else {
+        if (p < P4) col_phase<2, true, G::ELEMS, T>(s, LOGN1, G::C, 2 * p, tw, q, q2);
+        else col_phase<1, true, G::ELEMS, T>(s, LOGN1, G::C, LOGN1 - 1, tw, q, q2);
+      }
+    }
+    return;
+  }
   constexpr int REM = LOGN1 - 4;  // 0..4
   if (!INV) {
     col_phase<4, false, G::ELEMS, T>(s, LOGN1, G::C, REM, tw, q, q2);
