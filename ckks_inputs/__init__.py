@@ -134,6 +134,8 @@ CONFIGS = {
     "serve_n16": dict(logN=16, L_max=36, k=12, dnum=3, seed=5),
     # small chain for the toy CKKS semantic check: 6 + 2 primes, digit size 2
     "toy_n12": dict(logN=12, L_max=6, k=2, dnum=3, seed=7),
+    # digit size 1 with 24 digits: inner products over more than 16 digits
+    "n12_l24_k1": dict(logN=12, L_max=24, k=1, dnum=24, seed=8),
 }
 
 

@@ -315,8 +315,6 @@ int ckks_ctx_create(ckks_ctx** out, int logN, const uint32_t* h_q, int L_max, co
   const int alpha = (L_max + dnum - 1) / dnum;
   if (alpha != k) return fail(CKKS_EINVAL, "digit size ceil(L_max / dnum) must equal k");
   if (alpha > kMaxAlpha) return fail(CKKS_EUNSUPPORTED, "digit size above 16");
-  if ((L_max + alpha - 1) / alpha > 15)
-    return fail(CKKS_EUNSUPPORTED, "more than 15 digits (64-bit inner-product accumulator)");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail(CKKS_EINVAL, "no such HIP device");

@@ -183,6 +183,10 @@ __global__ __launch_bounds__(kWG) void k_inner_product(DevTab T, RowMap rm, cons
     const uint32_t* e = evk + (size_t)j * 2 * krows * N + (size_t)pi * N + n;
     a0 += (uint64_t)m * e[0];
     a1 += (uint64_t)m * e[krows * N];
+    if ((j & 7) == 7) {  // products below 2^60: fold before 16 of them add up
+      a0 = reduce64(a0, mc.q, mc.mu_hi, mc.mu_lo);
+      a1 = reduce64(a1, mc.q, mc.mu_hi, mc.mu_lo);
+    }
   }
   acc[(size_t)r * N + n] = reduce64(a0, mc.q, mc.mu_hi, mc.mu_lo);
   acc[((size_t)nrows + r) * N + n] = reduce64(a1, mc.q, mc.mu_hi, mc.mu_lo);

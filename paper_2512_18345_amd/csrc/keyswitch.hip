@@ -338,6 +338,16 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
       a1[4 * kk + 2] += (uint64_t)v[kk].z * e1.z;
       a1[4 * kk + 3] += (uint64_t)v[kk].w * e1.w;
     }
+    // Each product of canonical words is below q^2 < 2^60, so 16 of them fit
+    // a 64-bit sum; chains of more digits (digit size 1 allows up to 63) fold
+    // the sums back below q after every eighth digit.
+    if ((j & 7) == 7) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        a0[i] = reduce64(a0[i], q, m.mu_hi, m.mu_lo);
+        a1[i] = reduce64(a1[i], q, m.mu_hi, m.mu_lo);
+      }
+    }
   }
 
   // one reduction per output (the overflow-free accumulation of Sec. III-C2)
@@ -842,12 +852,14 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
 #pragma unroll
   for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
-    const uint4 w = canon4(lds_blk4(s, e), q, q2);
+    // w from [0, 4q) to [0, 2q): a + 2q - w < 3q < 2^32 goes straight into
+    // the Shoup product
+    const uint4 w = csub4(lds_blk4(s, e), q2);
     const uint4 a = av[kk], d = dv[kk];
-    const uint32_t o0 = csub(mul_shoup(a.x + q - w.x, pv.x, pv.y, q), q);
-    const uint32_t o1 = csub(mul_shoup(a.y + q - w.y, pv.x, pv.y, q), q);
-    const uint32_t o2 = csub(mul_shoup(a.z + q - w.z, pv.x, pv.y, q), q);
-    const uint32_t o3 = csub(mul_shoup(a.w + q - w.w, pv.x, pv.y, q), q);
+    const uint32_t o0 = csub(mul_shoup(a.x + q2 - w.x, pv.x, pv.y, q), q);
+    const uint32_t o1 = csub(mul_shoup(a.y + q2 - w.y, pv.x, pv.y, q), q);
+    const uint32_t o2 = csub(mul_shoup(a.z + q2 - w.z, pv.x, pv.y, q), q);
+    const uint32_t o3 = csub(mul_shoup(a.w + q2 - w.w, pv.x, pv.y, q), q);
     st4(out + e, make_uint4(csub(o0 + d.x, q), csub(o1 + d.y, q), csub(o2 + d.z, q), csub(o3 + d.w, q)));
   }
 }
@@ -980,10 +992,10 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    const uint4 v = canon4(lds_blk4(s, e), q, q2);
+    const uint4 v = csub4(lds_blk4(s, e), q2);  // [0, 2q): x + 2q - v < 3q
     const uint4 x = xs[kk];
-    st4(out + e, make_uint4(csub(mul_shoup(x.x + q - v.x, qi.x, qi.y, q), q), csub(mul_shoup(x.y + q - v.y, qi.x, qi.y, q), q),
-                   csub(mul_shoup(x.z + q - v.z, qi.x, qi.y, q), q), csub(mul_shoup(x.w + q - v.w, qi.x, qi.y, q), q)));
+    st4(out + e, make_uint4(csub(mul_shoup(x.x + q2 - v.x, qi.x, qi.y, q), q), csub(mul_shoup(x.y + q2 - v.y, qi.x, qi.y, q), q),
+                   csub(mul_shoup(x.z + q2 - v.z, qi.x, qi.y, q), q), csub(mul_shoup(x.w + q2 - v.w, qi.x, qi.y, q), q)));
   }
 }
 

@@ -307,6 +307,15 @@ __device__ __forceinline__ void lds_blk4_store(uint32_t* s, int e, uint4 v) {
   p[0] = v.x; p[1] = v.y; p[2] = v.z; p[3] = v.w;
 }
 
+// [0, 2m) -> [0, m) on each word
+__device__ __forceinline__ uint4 csub4(uint4 v, uint32_t m) {
+  v.x = csub(v.x, m);
+  v.y = csub(v.y, m);
+  v.z = csub(v.z, m);
+  v.w = csub(v.w, m);
+  return v;
+}
+
 __device__ __forceinline__ uint4 canon4(uint4 v, uint32_t q, uint32_t q2) {
   v.x = csub(csub(v.x, q2), q);
   v.y = csub(csub(v.y, q2), q);

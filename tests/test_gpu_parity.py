@@ -97,7 +97,7 @@ def test_tensor(name, L):
 
 
 # ---------------------------------------------------------------- key-switching stages
-LEVELS = [("n12_l4", 4), ("n12_l4", 1), ("n16_l36", 36), ("n16_l36", 13), ("n16_l36", 1)]
+LEVELS = [("n12_l4", 4), ("n12_l4", 1), ("n16_l36", 36), ("n16_l36", 13), ("n16_l36", 1), ("n12_l24_k1", 24)]
 
 
 @pytest.mark.parametrize("name,L", LEVELS)
@@ -141,7 +141,10 @@ def test_keyswitch(name, L):
 
 
 # ---------------------------------------------------------------- HMult / HRot / rescale
-@pytest.mark.parametrize("name,L", [("n12_l4", 4), ("n16_l36", 36), ("n16_l36", 25), ("n16_l36", 2)])
+# n12_l24_k1: digit size 1, up to 24 digits -- inner products over more than
+# 16 digits, whose 64-bit sums are folded as they run
+@pytest.mark.parametrize("name,L", [("n12_l4", 4), ("n16_l36", 36), ("n16_l36", 25), ("n16_l36", 2),
+                                    ("n12_l24_k1", 24), ("n12_l24_k1", 17)])
 def test_hmult(name, L):
     e = env(name)
     ct1 = e.rng.polys(2, e.Q(L), e.N)
@@ -152,7 +155,7 @@ def test_hmult(name, L):
     assert_same(host(out), O.hmult(e.par, ct1, ct2, L, rlk), "hmult")
 
 
-@pytest.mark.parametrize("name,L", [("n12_l4", 4), ("n16_l36", 36), ("n16_l36", 12)])
+@pytest.mark.parametrize("name,L", [("n12_l4", 4), ("n16_l36", 36), ("n16_l36", 12), ("n12_l24_k1", 24)])
 def test_hrot(name, L):
     e = env(name)
     ct = e.rng.polys(2, e.Q(L), e.N)
@@ -163,7 +166,8 @@ def test_hrot(name, L):
     assert_same(host(out), O.hrot(e.par, ct, L, rot, rotk), "hrot")
 
 
-@pytest.mark.parametrize("name,L,n", [("n12_l4", 4, 3), ("n16_l36", 36, 2), ("n16_l36", 20, 3)])
+@pytest.mark.parametrize("name,L,n", [("n12_l4", 4, 3), ("n16_l36", 36, 2), ("n16_l36", 20, 3),
+                                      ("n12_l24_k1", 24, 2)])
 def test_hrot_hoisted(name, L, n):
     e = env(name)
     ct = e.rng.polys(2, e.Q(L), e.N)
