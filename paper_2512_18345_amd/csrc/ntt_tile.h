@@ -3,11 +3,13 @@
 //
 // A limb of N = N1 * 256 words is viewed as N1 rows of 256.  The column pass
 // runs the first log2(N1) Cooley-Tukey stages on columns j + 256 r (r < N1);
-// a work-group tile holds C = 4096 / N1 adjacent columns.  The block pass runs
-// the last 8 stages inside contiguous 256-word blocks; a tile holds 16 blocks.
-// Inside a tile the stages run as radix-16 register phases (16 elements per
-// thread, four stages per LDS round trip) with lazy Shoup butterflies.  The
-// twiddle of butterfly group (m, i) is psi^brv(m + i) (inverse: psi^-brv(m + i)).
+// a work-group tile holds C adjacent columns (ColGeom).  The block pass runs
+// the last 8 stages inside contiguous 256-word blocks; a tile holds 16 blocks
+// (fewer for small grids).  Inside a tile the stages run as radix-16 register
+// phases (16 elements per thread, four stages per LDS round trip) or, for
+// small grids, radix-4 phases (4 elements per thread), with lazy Shoup
+// butterflies.  The twiddle of butterfly group (m, i) is psi^brv(m + i)
+// (inverse: psi^-brv(m + i)).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -294,7 +296,8 @@ __device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restri
 }
 
 // Block tiles: element e of the tile (e < 4096) is line e >> 8, pos e & 255.
-// Thread t owns tile elements 4t + 1024k .. +3 (k < 4) in the load/store/epilogue loops.
+// Thread t owns tile elements 4t + 1024k .. +3 (k < 4 for a 16-block tile,
+// k = 0 for a 4-block one) in the load/store/epilogue loops.
 __device__ __forceinline__ int blk_elem(int k) { return (threadIdx.x + k * kWG) * 4; }
 // (The block layout's 1-in-16 padding breaks 16-byte alignment, so these
 // LDS accesses stay 32-bit.)
