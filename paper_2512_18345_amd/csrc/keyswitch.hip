@@ -868,7 +868,8 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
 // Rescale: t = INTT_{q_{L-1}}(a_{L-1}); out_i = (a_i - NTT_{q_i}(t mod q_i)) q_{L-1}^-1
 // Scratch: t [2][N], u [2][L-1][N].
 // ============================================================================
-template <int LOGN1>
+// BPW blocks per work-group as in K1 (4: quarter tiles in radix-4 phases).
+template <int LOGN1, int BPW>
 __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, L = J.L, pi = L - 1;
@@ -877,19 +878,23 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
   __shared__ __align__(16) uint32_t s[kLds];
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
-  const int blk0 = blockIdx.x * 16;
+  constexpr int QPT = BPW / 4;  // quads per thread
+  const int blk0 = blockIdx.x * BPW;
   const uint32_t* in = J.a + ((size_t)c * L + pi) * N + blk0 * 256;
   uint32_t* t = J.ws + (size_t)c * N + blk0 * 256;
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
     lds_blk4_store(s, e, ld4(in + e));
   }
   __syncthreads();
-  blk_stages<true>(s, stw, q, q2);
+  if constexpr (BPW == 16)
+    blk_stages<true>(s, stw, q, q2);
+  else
+    blk_stages_r4<true, const uint2*, kWG>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
     st4(t + e, twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q));
   }
@@ -1105,8 +1110,9 @@ struct R3c { static constexpr auto fn = r3_ntt_cols<L1, CW, T>; };
 // Launch a column pass over `rows` rows of every job in its tile shape:
 // quarter-width tiles in radix-4 phases (four elements per thread) when four
 // times the work-groups still fit one per CU and the quarter is at least 32
-// columns (N <= 2^13); the narrowest tiles under kNarrowBelow work-groups
-// where `narrow` allows; else whole-line tiles of 16 elements per thread.
+// columns (N <= 2^13); the narrowest tiles (radix-4 phases too) under
+// kNarrowBelow work-groups where `narrow` allows; else whole-line tiles of 16
+// elements per thread.
 template <template <int, int, int> class KF, int L1, class JA>
 void col_launch(const Ctx& c, int stage, int rows, int njobs, bool narrow, hipStream_t st,
                 const KsConst& K, const JA& jobs) {
@@ -1120,8 +1126,10 @@ void col_launch(const Ctx& c, int stage, int rows, int njobs, bool narrow, hipSt
     }
   }
   if (narrow && TL * rows * njobs < kNarrowBelow) {
-    klaunch(c, stage, KF<L1, kColNarrow<L1>, kWG>::fn, dim3(ColGeom<L1, kColNarrow<L1>>::TILES, rows, njobs),
-            st, K, jobs);
+    // radix-4 phases, four elements per thread: four waves per SIMD
+    constexpr int CW = kColNarrow<L1>;
+    constexpr int T = ColGeom<L1, CW>::ELEMS / 4;
+    klaunch_b(c, stage, KF<L1, CW, T>::fn, dim3(ColGeom<L1, CW>::TILES, rows, njobs), T, st, K, jobs);
     return;
   }
   klaunch_b(c, stage, KF<L1, 0, kColThreads<L1>>::fn, dim3(TL, rows, njobs), kColThreads<L1>, st, K, jobs);
@@ -1239,7 +1247,10 @@ template <int L1>
 hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs, int njobs,
                        int Lmax, hipStream_t st) {
   const int tiles = c.N / kTile;
-  r1_intt_blks<L1><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
+  if (4 * tiles * 2 * njobs <= 256)  // quarter tiles while they fit one work-group per CU
+    r1_intt_blks<L1, 4><<<dim3(4 * tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
+  else
+    r1_intt_blks<L1, 16><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
   col_launch<R2c, L1>(c, -1, 2, njobs, true, st, K, jobs);
   col_launch<R3c, L1>(c, -1, 2 * (Lmax - 1), njobs, false, st, K, jobs);
   klaunch(c, CKKS_STAGE_RESCALE_NTT, r4_ntt_blks_combine<L1>, dim3(tiles, 2 * (Lmax - 1), njobs), st, K,
