@@ -1132,6 +1132,11 @@ void col_launch(const Ctx& c, int stage, int rows, int njobs, bool narrow, hipSt
     klaunch_b(c, stage, KF<L1, CW, T>::fn, dim3(ColGeom<L1, CW>::TILES, rows, njobs), T, st, K, jobs);
     return;
   }
+  if (narrow) {  // the INTT passes of about one work-group per CU: 8 elements per thread
+    constexpr int T = ColGeom<L1>::ELEMS / 8;
+    klaunch_b(c, stage, KF<L1, 0, T>::fn, dim3(TL, rows, njobs), T, st, K, jobs);
+    return;
+  }
   klaunch_b(c, stage, KF<L1, 0, kColThreads<L1>>::fn, dim3(TL, rows, njobs), kColThreads<L1>, st, K, jobs);
 }
 

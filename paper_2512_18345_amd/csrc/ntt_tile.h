@@ -34,7 +34,8 @@ struct ColGeom {
   static constexpr int C = CW ? CW : (kTile >> LOGN1) < 32 ? 32 : (kTile >> LOGN1);
   static constexpr int ELEMS = C * N1;             // 4096 or 8192 (fewer in quarter tiles)
   static constexpr int EPT = ELEMS / T;            // elements per thread
-  static_assert(EPT % 16 == 0 || EPT == 4, "groups of 16 elements per thread, or 4 in radix-4 phases");
+  static_assert(EPT % 16 == 0 || EPT == 8 || EPT == 4,
+                "groups of 16 elements per thread, or 8 / 4 in radix-8 / radix-4 phases");
   static constexpr int QUADS = ELEMS / (4 * T);    // 16-byte quads per thread in load/store
   static constexpr int LDS = ELEMS + N1;           // with the 16-word pad per 16 rows
   static constexpr int TILES = 256 / C;            // column tiles per limb
@@ -183,6 +184,23 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, ui
 template <int LOGN1, bool INV, int CW = 0, int T = kWG>
 __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_t q, uint32_t q2) {
   using G = ColGeom<LOGN1, CW, T>;
+  if constexpr (G::EPT == 8) {
+    // radix-8 phases (three bits each), then the remaining one or two bits
+    constexpr int P8 = LOGN1 / 3, REM = LOGN1 % 3;
+    constexpr int NPH = P8 + (REM ? 1 : 0);
+#pragma unroll
+    for (int p = 0; p < NPH; ++p) {
+      if (p) __syncthreads();
+      if (!INV) {
+        if (p < P8) col_phase<3, false, G::ELEMS, T>(s, LOGN1, G::C, LOGN1 - 3 - 3 * p, tw, q, q2);
+        else col_phase<(REM ? REM : 1), false, G::ELEMS, T>(s, LOGN1, G::C, 0, tw, q, q2);
+      } else {
+        if (REM && p == 0) col_phase<(REM ? REM : 1), true, G::ELEMS, T>(s, LOGN1, G::C, 0, tw, q, q2);
+        else col_phase<3, true, G::ELEMS, T>(s, LOGN1, G::C, REM + 3 * (p - (REM ? 1 : 0)), tw, q, q2);
+      }
+    }
+    return;
+  }
   if constexpr (G::EPT == 4) {
     // radix-4 phases (two bits each), a radix-2 phase for an odd log2 N1
     constexpr int P4 = LOGN1 / 2, ODD = LOGN1 & 1;

@@ -204,10 +204,11 @@ def test_errors_are_reported_not_launched():
 # ---------------------------------------------------------------- every ring degree / digit shape
 # The fused pipeline is compiled per column-pass shape (N = 2^12 .. 2^16) and per
 # digit size; these cases reach the shapes the cases above do not: N = 2^13,
-# 2^14, 2^15 on the 36 + 12 chain (partial and full digits) and the toy chain
-# (N = 2^12, 6 + 2 primes, digit size 2, three digits).
-@pytest.mark.parametrize("name,logN,L", [("n16_l36", 13, 7), ("n16_l36", 14, 13), ("n16_l36", 15, 30),
-                                         ("toy_n12", None, 6), ("toy_n12", None, 3)])
+# 2^14, 2^15 on the 36 + 12 chain (partial and full digits; each ring degree's
+# radix schedule of the column passes, small-grid and whole-line) and the toy
+# chain (N = 2^12, 6 + 2 primes, digit size 2, three digits).
+@pytest.mark.parametrize("name,logN,L", [("n16_l36", 13, 7), ("n16_l36", 14, 13), ("n16_l36", 14, 36),
+                                         ("n16_l36", 15, 30), ("toy_n12", None, 6), ("toy_n12", None, 3)])
 def test_hmult_hrot_rescale_every_shape(name, logN, L):
     e = env(name, logN)
     ct1 = e.rng.polys(2, e.Q(L), e.N)
