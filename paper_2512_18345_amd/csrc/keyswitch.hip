@@ -91,12 +91,12 @@ __device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const ModC& m
 // The QPT quads (words base + blk_elem(kk) .. +3) of row r of the polynomial
 // a job key-switches: d (PLAIN), c1 c1' (HMULT), sigma(c1) (HROT / HOIST).
 // Every load of a quad is issued before any of them is used.
-template <int QPT = 4>
+template <int QPT = 4, int T = kWG>
 __device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, size_t N, int logN,
                                          const ModC& m, uint4 d[QPT]) {
   if (J.kind == KS_PLAIN) {
 #pragma unroll
-    for (int kk = 0; kk < QPT; ++kk) d[kk] = ld4(J.a + (size_t)r * N + base + blk_elem(kk));
+    for (int kk = 0; kk < QPT; ++kk) d[kk] = ld4(J.a + (size_t)r * N + base + blk_elem<T>(kk));
     return;
   }
   const size_t row1 = (size_t)(J.L + r) * N;
@@ -104,8 +104,8 @@ __device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, s
     uint4 x[QPT], y[QPT];
 #pragma unroll
     for (int kk = 0; kk < QPT; ++kk) {
-      x[kk] = ld4(J.a + row1 + base + blk_elem(kk));
-      y[kk] = ld4(J.b + row1 + base + blk_elem(kk));
+      x[kk] = ld4(J.a + row1 + base + blk_elem<T>(kk));
+      y[kk] = ld4(J.b + row1 + base + blk_elem<T>(kk));
     }
 #pragma unroll
     for (int kk = 0; kk < QPT; ++kk)
@@ -116,7 +116,7 @@ __device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, s
   const uint32_t* src = J.a + row1;
 #pragma unroll
   for (int kk = 0; kk < QPT; ++kk) {
-    const uint32_t n = base + blk_elem(kk);
+    const uint32_t n = base + blk_elem<T>(kk);
     d[kk] = make_uint4(ld1(src + auto_src(n, J.gal, logN)), ld1(src + auto_src(n + 1, J.gal, logN)),
                        ld1(src + auto_src(n + 2, J.gal, logN)), ld1(src + auto_src(n + 3, J.gal, logN)));
   }
@@ -128,8 +128,8 @@ __device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, s
 
 // BPW blocks per work-group: 16 (a 4096-word tile, radix-16 phases) or, for
 // small grids, 4 (a quarter tile, one quad per thread, radix-4 phases).
-template <int LOGN1, int BPW>
-__global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA) {
+template <int LOGN1, int BPW, int EPT = (BPW == 16 ? 16 : 4)>
+__global__ __launch_bounds__(BPW * 256 / EPT) void k1_intt_blks(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const int r = blockIdx.y;
   if (J.kind == KS_HOIST || r >= J.L) return;
@@ -139,31 +139,34 @@ __global__ __launch_bounds__(kWG) void k1_intt_blks(KsConst K, JobArg<KsJob> JA)
   const ModC m = ldc(K.T.mod + r);
   const uint32_t q = m.q, q2 = 2 * q;
   __shared__ uint2 stw[256];
-  stage_tw(stw, K.T.blk_itw(r), 256);
-  constexpr int QPT = BPW / 4;  // quads per thread
+  stage_tw(stw, K.T.blk_itw(r), 256);  // (T >= 256)
+  constexpr int T = BPW * 256 / EPT;  // threads
+  constexpr int QPT = EPT / 4;        // quads per thread
   const int blk0 = blockIdx.x * BPW;
   const uint32_t base = blk0 * 256;
   const KsView V = ks_view(J, K, N);
   uint32_t* de = V.de + (size_t)r * N + base;
   // all loads first: a store to de could alias the next quad's source
   uint4 d[QPT];
-  load_d16<QPT>(J, r, base, N, logN, m, d);
+  load_d16<QPT, T>(J, r, base, N, logN, m, d);
 #pragma unroll
   for (int kk = 0; kk < QPT; ++kk) {
-    const int e = blk_elem(kk);
+    const int e = blk_elem<T>(kk);
     lds_blk4_store(s, e, d[kk]);
     if (J.kind != KS_PLAIN) st4(de + e, d[kk]);
   }
   __syncthreads();
-  if constexpr (BPW == 16)
+  if constexpr (EPT == 16)
     blk_stages<true>(s, stw, q, q2);
+  else if constexpr (EPT == 8)
+    blk_stages_r8<true, const uint2*, T>(s, stw, q, q2);
   else
-    blk_stages_r4<true, const uint2*, kWG>(s, stw, q, q2);
+    blk_stages_r4<true, const uint2*, T>(s, stw, q, q2);
   __syncthreads();
   uint32_t* y = V.y + (size_t)r * N + base;
 #pragma unroll
   for (int kk = 0; kk < QPT; ++kk) {
-    const int e = blk_elem(kk);
+    const int e = blk_elem<T>(kk);
     st4(y + e, twist4(lds_blk4(s, e), K.T.blk_itwist(r, blk0 + (e >> 8)), e & 255, q));
   }
 }
@@ -1156,7 +1159,7 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     if (4 * tiles * Lmax * njobs <= 256)  // quarter tiles still one work-group per CU
       klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 4>, dim3(4 * tiles, Lmax, njobs), st, K, jobs);
     else
-      klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16>, dim3(tiles, Lmax, njobs), st, K, jobs);
+      klaunch_b(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16, 8>, dim3(tiles, Lmax, njobs), 512, st, K, jobs);
     col_launch<K2c, L1>(c, CKKS_STAGE_INTT_COLS, Lmax, njobs, true, st, K, jobs);
     e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
     if (e != hipSuccess) return e;

@@ -233,6 +233,25 @@ __device__ __forceinline__ void col_stages(uint32_t* s, const uint2* tw, uint32_
   }
 }
 
+// The eight block stages as radix-8, radix-8 and radix-4 phases, for 16-block
+// tiles of T = 512 threads with eight elements each.
+template <bool INV, class TW, int T>
+__device__ __forceinline__ void blk_stages_r8(uint32_t* s, const TW& tw, uint32_t q, uint32_t q2) {
+  if (!INV) {
+    blk_phase<3, false, TW, 8, T>(s, 5, tw, q, q2);
+    __syncthreads();
+    blk_phase<3, false, TW, 8, T>(s, 2, tw, q, q2);
+    __syncthreads();
+    blk_phase<2, false, TW, 8, T>(s, 0, tw, q, q2);
+  } else {
+    blk_phase<2, true, TW, 8, T>(s, 0, tw, q, q2);
+    __syncthreads();
+    blk_phase<3, true, TW, 8, T>(s, 2, tw, q, q2);
+    __syncthreads();
+    blk_phase<3, true, TW, 8, T>(s, 5, tw, q, q2);
+  }
+}
+
 // The eight block stages as four radix-4 phases, for tiles of T threads with
 // four elements each (small grids: a quarter as many butterflies per thread
 // as the radix-16 form, on four times the work-groups).
@@ -316,7 +335,8 @@ __device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restri
 // Block tiles: element e of the tile (e < 4096) is line e >> 8, pos e & 255.
 // Thread t owns tile elements 4t + 1024k .. +3 (k < 4 for a 16-block tile,
 // k = 0 for a 4-block one) in the load/store/epilogue loops.
-__device__ __forceinline__ int blk_elem(int k) { return (threadIdx.x + k * kWG) * 4; }
+template <int T = kWG>
+__device__ __forceinline__ int blk_elem(int k) { return (threadIdx.x + k * T) * 4; }
 // (The block layout's 1-in-16 padding breaks 16-byte alignment, so these
 // LDS accesses stay 32-bit.)
 __device__ __forceinline__ uint4 lds_blk4(const uint32_t* s, int e) {
