@@ -265,7 +265,8 @@ def main():
 
 def small_hmult_latency(P, ci, reps):
     """Latency distribution of one HMult at N=2^12 with 4 + 1 primes, dnum 4:
-    each call bracketed by events on its stream (a launch-latency-bound case)."""
+    each call bracketed by events on its stream (a launch-latency-bound case),
+    as a plain ckks_hmult call and as a one-job graph batch (graph_p50/p99)."""
     import torch
     spec = ci.get("n12_l4")
     rng = ci.Rng(spec.seed)
@@ -293,9 +294,28 @@ def small_hmult_latency(P, ci, reps):
         e1.synchronize()
         lat.append(e0.elapsed_time(e1) * 1e3)
     lat = np.array(lat)
+    # the same HMult as a one-job graph batch: one submission per call
+    b = P.ckks_batch_create(ctx.handle, [dict(op=P.JOB["HMULT"], L=L, in0=ct1, in1=ct2, key=rlk, out=out)],
+                            use_graph=True)
+    for _ in range(20):
+        P.ckks_batch_launch(b, stream)
+    torch.cuda.synchronize()
+    glat = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.ckks_batch_launch(b, stream)
+        e1.record(stream)
+        e1.synchronize()
+        glat.append(e0.elapsed_time(e1) * 1e3)
+    glat = np.array(glat)
+    P.ckks_batch_destroy(b)
     ctx.close()
     return {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
-            "reps": int(reps)}
+            "reps": int(reps),
+            "graph_p50": round(float(np.percentile(glat, 50)), 2),
+            "graph_p99": round(float(np.percentile(glat, 99)), 2)}
 
 
 def _op_limbs(op, L, k, beta):
