@@ -333,10 +333,19 @@ __device__ __forceinline__ void store_cols(const uint32_t* s, uint32_t* __restri
 }
 
 // Block tiles: element e of the tile (e < 4096) is line e >> 8, pos e & 255.
-// Thread t owns tile elements 4t + 1024k .. +3 (k < 4 for a 16-block tile,
-// k = 0 for a 4-block one) in the load/store/epilogue loops.
+// blk_elem(k) is the first element of the k-th quad of thread t (T threads,
+// tiles of a multiple of four lines) in the load/store/epilogue loops.  Quad
+// number t + kT is split as (g, w, l) = (bits 8.., bits 6-7, bits 0-5): the
+// 64 lanes of a wave instruction take 16 consecutive quads (256 bytes) from
+// each of four lines, line 4g + l / 16, quad 16w + l % 16.  In the padded
+// layout the 64 lanes then fall on 64 different banks for each word of the
+// quad; 64 consecutive quads of one line would meet up to four to a bank.
 template <int T = kWG>
-__device__ __forceinline__ int blk_elem(int k) { return (threadIdx.x + k * T) * 4; }
+__device__ __forceinline__ int blk_elem(int k) {
+  const int qi = threadIdx.x + k * T;
+  const int g = qi >> 8, w = (qi >> 6) & 3, l = qi & 63;
+  return ((4 * g + (l >> 4)) << 8) | ((16 * w + (l & 15)) << 2);
+}
 // (The block layout's 1-in-16 padding breaks 16-byte alignment, so these
 // LDS accesses stay 32-bit.)
 __device__ __forceinline__ uint4 lds_blk4(const uint32_t* s, int e) {
