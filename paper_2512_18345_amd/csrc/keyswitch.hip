@@ -1092,8 +1092,7 @@ hipError_t small_dispatch(int v, const Ctx& c, dim3 g, hipStream_t st, const KsC
 // row segments cost more than the extra CUs gain (K2: 12.1 -> 14.1 us).
 constexpr int kNarrowBelow = 128;
 // Threads of the column passes over whole-line tiles: 16 elements per thread
-// (512 threads for the 8192-word tiles at N = 2^16; K2 and K6, launches of
-// about one work-group per CU, then run two waves per SIMD).
+// (512 threads for the 8192-word tiles at N = 2^16).
 template <int L1>
 constexpr int kColThreads = ColGeom<L1>::ELEMS / 16;
 
@@ -1113,11 +1112,13 @@ struct R3c { static constexpr auto fn = r3_ntt_cols<L1, CW, T>; };
 // Launch a column pass over `rows` rows of every job in its tile shape:
 // quarter-width tiles in radix-4 phases (four elements per thread) when four
 // times the work-groups still fit one per CU and the quarter is at least 32
-// columns (N <= 2^13); the narrowest tiles (radix-4 phases too) under
-// kNarrowBelow work-groups where `narrow` allows; else whole-line tiles of 16
-// elements per thread.
+// columns (N <= 2^13).  Otherwise a `sparse` pass (one whose launches have
+// about one work-group per CU or fewer: the INTT passes K2, K6 and the
+// rescale's) takes the narrowest tiles in radix-4 phases under kNarrowBelow
+// work-groups and whole-line tiles with eight elements per thread in radix-8
+// phases above; the others take whole-line tiles of 16 elements per thread.
 template <template <int, int, int> class KF, int L1, class JA>
-void col_launch(const Ctx& c, int stage, int rows, int njobs, bool narrow, hipStream_t st,
+void col_launch(const Ctx& c, int stage, int rows, int njobs, bool sparse, hipStream_t st,
                 const KsConst& K, const JA& jobs) {
   constexpr int TL = ColGeom<L1>::TILES;
   if constexpr (ColGeom<L1>::C / 4 >= 32) {
@@ -1128,14 +1129,14 @@ void col_launch(const Ctx& c, int stage, int rows, int njobs, bool narrow, hipSt
       return;
     }
   }
-  if (narrow && TL * rows * njobs < kNarrowBelow) {
+  if (sparse && TL * rows * njobs < kNarrowBelow) {
     // radix-4 phases, four elements per thread: four waves per SIMD
     constexpr int CW = kColNarrow<L1>;
     constexpr int T = ColGeom<L1, CW>::ELEMS / 4;
     klaunch_b(c, stage, KF<L1, CW, T>::fn, dim3(ColGeom<L1, CW>::TILES, rows, njobs), T, st, K, jobs);
     return;
   }
-  if (narrow) {  // the INTT passes of about one work-group per CU: 8 elements per thread
+  if (sparse) {  // 8 elements per thread: four waves per SIMD
     constexpr int T = ColGeom<L1>::ELEMS / 8;
     klaunch_b(c, stage, KF<L1, 0, T>::fn, dim3(TL, rows, njobs), T, st, K, jobs);
     return;
