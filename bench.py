@@ -331,7 +331,7 @@ def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
     batch (one captured graph) vs 8 single calls; (b) the 64-job mixed-level
     batch (levels uniform in 4..36; HMult 0.4, HRot 0.4 over 8 rotation keys,
     rescale 0.2) as one captured graph.  Each batch is timed with the default
-    plan and again after ckks_batch_tune picked its plan."""
+    plan and again after ckks_batch_tune picked its plan and kernel schedule."""
     import torch
     N, L, k = spec.N, spec.L_max, spec.k
     limb = N * LIMB_BYTES
@@ -352,7 +352,7 @@ def batched_numbers(P, ci, ctx, spec, dev, d_ct1, d_ct2, d_rlk, reps):
         tuned = timed(lambda: P.ckks_batch_launch(b, stream), n_ks)
         log = [[p["jobs_per_launch"], p["streams"], p["split"], round(us, 1)]
                for p, us in P.ckks_batch_tune_log(b)]
-        return default, tuned, dict(plan, candidates_B_S_split_us=log)
+        return default, tuned, dict(plan, schedule=P.ckks_batch_get_schedule(b), candidates_B_S_split_us=log)
 
     # (a) same work, batched vs single-op
     outs = [torch.empty((2, L, N), dtype=torch.int32, device="cuda") for _ in range(8)]

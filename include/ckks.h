@@ -330,20 +330,31 @@ int ckks_batch_get_plan(const ckks_batch *batch, ckks_batch_plan *plan);
  * CKKS_EUNSUPPORTED (streams > 1 on a graph batch), CKKS_EHIP. */
 int ckks_batch_set_plan(ckks_batch *batch, const ckks_batch_plan *plan);
 /*
+ * A batch's own kernel schedule (struct ckks_schedule above): the context's
+ * at creation; set here or by ckks_batch_tune.  Setting re-captures the
+ * graph of a graph batch and must not overlap a launch of the same batch.
+ * Errors: CKKS_EINVAL (bad schedule, as for ckks_ctx_set_schedule), CKKS_EHIP.
+ */
+int ckks_batch_get_schedule(const ckks_batch *batch, ckks_schedule *sched);
+int ckks_batch_set_schedule(ckks_batch *batch, const ckks_schedule *sched);
+/*
  * Autotuner: times candidate plans (jobs_per_launch in {all, 32, 16, 8, 4, 2}
  * below the job count, streams 1..4 up to the number of groups (1 for a
- * graph batch), split 0/1/2),
- * each as one warm-up launch then `reps` launches between two events on
- * `stream`, and keeps the fastest (graph batches are re-captured and timed as
- * graph launches).  Runs the batch up to 72 x (reps + 1) times and
- * synchronises `stream`: outputs are written, inputs only read.  best /
- * best_us (either may be NULL) receive the chosen plan and its time per
- * launch in microseconds.  On error the previous plan is kept.
+ * graph batch), split 0/1/2) under the batch's schedule, then, under the
+ * best plan, up to four other kernel schedules ({12, 6, 128}, {6, 4, 128},
+ * {4, 6, 128}, {12, 12, 128}): each candidate as one warm-up launch then
+ * `reps` launches between two events on `stream`; keeps the fastest plan and
+ * schedule (graph batches are re-captured and timed as graph launches).
+ * Runs the batch up to 76 x (reps + 1) times and synchronises `stream`:
+ * outputs are written, inputs only read.  best / best_us (either may be
+ * NULL) receive the chosen plan and its time per launch in microseconds;
+ * ckks_batch_get_schedule gives the chosen schedule.  On error the previous
+ * plan and schedule are kept.
  */
 int ckks_batch_tune(ckks_batch *batch, int reps, void *stream, ckks_batch_plan *best,
                     float *best_us);
-/* The candidates of the last ckks_batch_tune and their microseconds per
- * launch, in the order tried: *n receives their number, the first
+/* The plan candidates of the last ckks_batch_tune and their microseconds
+ * per launch, in the order tried: *n receives their number, the first
  * min(cap, *n) are copied to plans / us. */
 int ckks_batch_tune_log(const ckks_batch *batch, ckks_batch_plan *plans, float *us, int cap,
                         int *n);

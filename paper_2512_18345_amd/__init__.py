@@ -23,7 +23,7 @@ __all__ = [
     "ckks_batch_tune", "ckks_batch_tune_log", "ckks_stats", "ckks_server_create", "ckks_server_submit",
     "ckks_server_poll", "ckks_server_drain", "ckks_server_stats", "ckks_server_times",
     "ckks_server_destroy", "ckks_pmult_sum", "ckks_add", "ckks_schedule", "ckks_ctx_get_schedule",
-    "ckks_ctx_set_schedule", "ckks_ctx_tune",
+    "ckks_ctx_set_schedule", "ckks_ctx_tune", "ckks_batch_get_schedule", "ckks_batch_set_schedule",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -112,6 +112,8 @@ _SIGS = {
     "ckks_ctx_set_schedule": [_vp, _vp],
     "ckks_ctx_tune": [_vp, _i, _i, _vp, _vp, _vp],
     "ckks_batch_set_plan": [_vp, _vp],
+    "ckks_batch_get_schedule": [_vp, _vp],
+    "ckks_batch_set_schedule": [_vp, _vp],
     "ckks_batch_tune": [_vp, _i, _vp, _vp, _vp],
     "ckks_batch_tune_log": [_vp, _vp, _vp, _i, ctypes.POINTER(_i)],
     "ckks_pmult_sum": [_vp, _vp, _vp, _i, _i, _vp, _vp],
@@ -317,6 +319,17 @@ def ckks_ctx_tune(ctx, L, reps=3, stream=None):
     _check(lib().ckks_ctx_tune(ctx, int(L), int(reps), _stream(stream),
                                ctypes.cast(ctypes.byref(s), _vp), ctypes.cast(ctypes.byref(us), _vp)))
     return s.as_dict(), float(us.value)
+
+
+def ckks_batch_get_schedule(batch) -> dict:
+    s = ckks_schedule()
+    _check(lib().ckks_batch_get_schedule(batch, ctypes.cast(ctypes.byref(s), _vp)))
+    return s.as_dict()
+
+
+def ckks_batch_set_schedule(batch, bconv_up_rows=12, bconv_down_rows=6, small_grid=128):
+    s = ckks_schedule(int(bconv_up_rows), int(bconv_down_rows), int(small_grid), 0)
+    _check(lib().ckks_batch_set_schedule(batch, ctypes.cast(ctypes.byref(s), _vp)))
 
 
 def ckks_batch_tune_log(batch) -> list:

@@ -160,7 +160,7 @@ int run_one(const Ctx& c, int kind, int L, uint32_t gal, const uint32_t* a, cons
   JobArg<KsJob> ja{};
   ja.table = nullptr;
   ja.inl[0] = KsJob{kind, L, gal, 0, a, b, key, out, (uint32_t*)ws};
-  CKKS_TRY(ks_launch(c, ja, 1, L, true, false, st), "key-switching pipeline");
+  CKKS_TRY(ks_launch(c, c.sched, ja, 1, L, true, false, st), "key-switching pipeline");
   return CKKS_OK;
 }
 
@@ -194,6 +194,7 @@ struct ckks_batch {
   hipEvent_t join[kMaxBranches] = {};
   std::vector<hipEvent_t> gev;  // fork / join events of the split, two per launch group
   std::vector<std::pair<ckks_batch_plan, float>> tune_log;  // last ckks_batch_tune: plan, us
+  Ctx::Sched sched;  // kernel schedule of this batch's launches (the context's at creation)
 };
 
 namespace {
@@ -222,7 +223,7 @@ hipError_t batch_enqueue(ckks_batch* b, hipStream_t st) {
     const KsSplit sp = b->plan.split
                            ? KsSplit{b->side[br], b->gev[2 * group], b->gev[2 * group + 1], b->plan.split == 2}
                            : KsSplit{};
-    if ((e = ks_launch(c, ka, std::min(B, b->n_ks - s0), b->L_ks[s0], true, false, on(br), sp)) !=
+    if ((e = ks_launch(c, b->sched, ka, std::min(B, b->n_ks - s0), b->L_ks[s0], true, false, on(br), sp)) !=
         hipSuccess)
       return e;
   }
@@ -518,7 +519,7 @@ int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int*
     for (int t = 0; t < cnt; ++t)
       ja.inl[t] = KsJob{KS_HOIST, L, galois(c, h_rots[i0 + t]), 0, ct, M, h_rotks[i0 + t],
                         h_outs[i0 + t], job_ws[t]};
-    CKKS_TRY(ks_launch(c, ja, cnt, L, false, true, st), "hoisted rotations");
+    CKKS_TRY(ks_launch(c, c.sched, ja, cnt, L, false, true, st), "hoisted rotations");
   }
   return CKKS_OK;
 }
@@ -683,6 +684,7 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
   b->n_rs = (int)rs.size();
   b->Lmax_rs = Lrs;
   b->use_graph = use_graph != 0;
+  b->sched = ctx->c.sched;
   const size_t tab = round_up(sizeof(KsJob) * ks.size()) + round_up(sizeof(RsJob) * rs.size());
   if (hipMalloc(&b->d_ws, ws) != hipSuccess ||
       (!ks.empty() && hipMalloc(&b->d_ks, sizeof(KsJob) * ks.size()) != hipSuccess) ||
@@ -756,6 +758,22 @@ int ckks_batch_set_plan(ckks_batch* b, const ckks_batch_plan* plan) {
   return CKKS_OK;
 }
 
+int ckks_batch_get_schedule(const ckks_batch* b, ckks_schedule* sched) {
+  if (!b || !sched) return fail(CKKS_EINVAL, "null argument");
+  *sched = ckks_schedule{b->sched.up_rows, b->sched.down_rows, b->sched.small_grid, 0};
+  return CKKS_OK;
+}
+
+int ckks_batch_set_schedule(ckks_batch* b, const ckks_schedule* sched) {
+  if (!b || !sched) return fail(CKKS_EINVAL, "null argument");
+  if (!sched_ok(*sched))
+    return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12} and 0 <= small_grid <= 65535");
+  DeviceGuard g(b->c->device);
+  b->sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid};
+  if (b->use_graph) CKKS_TRY(batch_capture(b), "re-capturing the batch graph");
+  return CKKS_OK;
+}
+
 int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best, float* best_us) {
   if (!b || reps < 1 || reps > 1000) return fail(CKKS_EINVAL, "need a batch and 1 <= reps <= 1000");
   DeviceGuard g(b->c->device);
@@ -769,12 +787,30 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
     (void)hipEventDestroy(t0);
     return fail(CKKS_EHIP, "hipEventCreate failed");
   }
+  // one warm-up and `reps` timed launches of the batch as it stands
+  // (re-captured first for a graph batch); microseconds per launch
+  auto time_it = [&](float* us) -> hipError_t {
+    hipError_t te = b->use_graph ? batch_capture(b) : hipSuccess;
+    auto launch = [&]() { return b->exec ? hipGraphLaunch(b->exec, st) : batch_enqueue(b, st); };
+    if (te == hipSuccess) te = launch();
+    if (te == hipSuccess) te = hipEventRecord(t0, st);
+    for (int r = 0; r < reps && te == hipSuccess; ++r) te = launch();
+    if (te == hipSuccess) te = hipEventRecord(t1, st);
+    if (te == hipSuccess) te = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (te == hipSuccess) te = hipEventElapsedTime(&ms, t0, t1);
+    *us = 1e3f * ms / reps;
+    return te;
+  };
   const ckks_batch_plan start = b->plan;
+  const Ctx::Sched start_sched = b->sched;
   ckks_batch_plan top = start;
+  Ctx::Sched top_sched = start_sched;
   b->tune_log.clear();
   float top_us = -1.f;
   hipError_t e = hipSuccess;
   const int max_streams = b->use_graph ? 1 : kMaxBranches;
+  // 1) launch plans under the batch's schedule
   for (int B : sizes) {
     const int groups = B ? (b->n_ks + B - 1) / B : 1;
     if ((e = batch_events(b, ckks_batch_plan{B, 1, 1, 0})) != hipSuccess) break;
@@ -782,17 +818,8 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
       if (S > 1 && S > groups + (b->n_rs ? 1 : 0)) break;
       for (int split = 0; split <= 2 && e == hipSuccess; ++split) {
         b->plan = ckks_batch_plan{B, S, split, 0};
-        if (b->use_graph && (e = batch_capture(b)) != hipSuccess) break;
-        auto launch = [&]() { return b->exec ? hipGraphLaunch(b->exec, st) : batch_enqueue(b, st); };
-        if ((e = launch()) != hipSuccess) break;  // warm-up
-        if ((e = hipEventRecord(t0, st)) != hipSuccess) break;
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
-        if (e != hipSuccess || (e = hipEventRecord(t1, st)) != hipSuccess ||
-            (e = hipEventSynchronize(t1)) != hipSuccess)
-          break;
-        float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
-        const float us = 1e3f * ms / reps;
+        float us = 0.f;
+        if ((e = time_it(&us)) != hipSuccess) break;
         b->tune_log.emplace_back(b->plan, us);
         if (top_us < 0.f || us < top_us) {
           top_us = us;
@@ -801,10 +828,32 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
       }
     }
   }
+  // 2) kernel schedules under the best plan: a batch's grids are larger than
+  // a single operation's, so the context's schedule need not suit it
+  if (e == hipSuccess) {
+    b->plan = top;
+    e = batch_events(b, top);
+    const Ctx::Sched cands[] = {{12, 6, 128}, {6, 4, 128}, {4, 6, 128}, {12, 12, 128}};
+    for (const Ctx::Sched& cs : cands) {
+      if (e != hipSuccess) break;
+      if (cs.up_rows == start_sched.up_rows && cs.down_rows == start_sched.down_rows &&
+          cs.small_grid == start_sched.small_grid)
+        continue;  // timed in the plan search
+      b->sched = cs;
+      float us = 0.f;
+      if ((e = time_it(&us)) != hipSuccess) break;
+      if (us < top_us) {
+        top_us = us;
+        top_sched = cs;
+      }
+    }
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   b->plan = e == hipSuccess ? top : start;
-  const hipError_t ce = b->use_graph ? batch_capture(b) : hipSuccess;
+  b->sched = e == hipSuccess ? top_sched : start_sched;
+  hipError_t ce = batch_events(b, b->plan);
+  if (ce == hipSuccess && b->use_graph) ce = batch_capture(b);
   if (e != hipSuccess) return hip_fail(e, "timing candidate plans");
   if (ce != hipSuccess) return hip_fail(ce, "re-capturing the batch graph");
   if (best) *best = top;

@@ -74,10 +74,11 @@ size_t ks_hoist_ws_words(const Ctx& c, int L);  // KS_HOIST jobs only (no ModUp 
 size_t rs_ws_words(const Ctx& c, int L);
 
 // Enqueue the key-switching pipeline for njobs jobs whose largest level is
-// Lmax.  with_modup: some job is not KS_HOIST (stage 1 runs); with_hoist: some
-// job is KS_HOIST.
-hipError_t ks_launch(const Ctx& c, const JobArg<KsJob>& jobs, int njobs, int Lmax, bool with_modup,
-                     bool with_hoist, hipStream_t st, const KsSplit& sp = KsSplit{});
+// Lmax under kernel schedule sc (the context's, or a batch's own).
+// with_modup: some job is not KS_HOIST (stage 1 runs); with_hoist: some job
+// is KS_HOIST.
+hipError_t ks_launch(const Ctx& c, const Ctx::Sched& sc, const JobArg<KsJob>& jobs, int njobs, int Lmax,
+                     bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp = KsSplit{});
 // Enqueue rescale (drop the top prime) for njobs jobs.
 hipError_t rs_launch(const Ctx& c, const JobArg<RsJob>& jobs, int njobs, int Lmax, hipStream_t st);
 

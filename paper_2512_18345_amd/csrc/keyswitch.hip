@@ -1059,29 +1059,29 @@ struct K7fn {
 template <int A>
 struct K3 {
   static void run(const Ctx& c, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
-                  int gr) {
-    launch_bconv<K3fn, A>(c, CKKS_STAGE_BCONV_UP, c.sched.up_rows, g, st, K, J, gr);
+                  int gr, int rows) {
+    launch_bconv<K3fn, A>(c, CKKS_STAGE_BCONV_UP, rows, g, st, K, J, gr);
   }
 };
 template <int A>
 struct K7 {
   static void run(const Ctx& c, dim3 g, hipStream_t st, const KsConst& K, const JobArg<KsJob>& J,
-                  int gr) {
-    launch_bconv<K7fn, A>(c, CKKS_STAGE_BCONV_DOWN, c.sched.down_rows, g, st, K, J, gr);
+                  int gr, int rows) {
+    launch_bconv<K7fn, A>(c, CKKS_STAGE_BCONV_DOWN, rows, g, st, K, J, gr);
   }
 };
 
 template <template <int> class F, int V>
 hipError_t small_dispatch(int v, const Ctx& c, dim3 g, hipStream_t st, const KsConst& K,
-                          const JobArg<KsJob>& J, int gr) {
+                          const JobArg<KsJob>& J, int gr, int rows) {
   if constexpr (V > kMaxAlpha) {
     return hipErrorInvalidValue;
   } else {
     if (v == V) {
-      F<V>::run(c, g, st, K, J, gr);
+      F<V>::run(c, g, st, K, J, gr, rows);
       return hipSuccess;
     }
-    return small_dispatch<F, V + 1>(v, c, g, st, K, J, gr);
+    return small_dispatch<F, V + 1>(v, c, g, st, K, J, gr, rows);
   }
 }
 
@@ -1145,14 +1145,15 @@ void col_launch(const Ctx& c, int stage, int rows, int njobs, bool sparse, hipSt
 }
 
 template <int L1>
-hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs, int njobs,
-                       int Lmax, bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp) {
+hipError_t ks_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, const JobArg<KsJob>& jobs,
+                       int njobs, int Lmax, bool with_modup, bool with_hoist, hipStream_t st,
+                       const KsSplit& sp) {
   const int Rmax = Lmax + c.k;
   const int tiles = c.N / kTile;
   const int cols = c.N / (4 * kWG);  // BConv: four coefficients per thread
   const int bmax = c.beta(Lmax);
   auto rows_of = [](int r) { return r == 2 || r == 4 || r == 6 ? r : 12; };
-  const int up_rows = rows_of(c.sched.up_rows), down_rows = rows_of(c.sched.down_rows);
+  const int up_rows = rows_of(sc.up_rows), down_rows = rows_of(sc.down_rows);
   const int up_groups = (Rmax + up_rows - 1) / up_rows;
   const int down_groups = (Lmax + down_rows - 1) / down_rows;
   hipError_t e;
@@ -1162,7 +1163,8 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
     else
       klaunch_b(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16, 8>, dim3(tiles, Lmax, njobs), 512, st, K, jobs);
     col_launch<K2c, L1>(c, CKKS_STAGE_INTT_COLS, Lmax, njobs, true, st, K, jobs);
-    e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups);
+    e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups,
+                              up_rows);
     if (e != hipSuccess) return e;
     col_launch<K4c, L1>(c, CKKS_STAGE_NTT_COLS_UP, bmax * Rmax, njobs, false, st, K, jobs);
   }
@@ -1173,7 +1175,7 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   auto k5 = [&](int stage, int part, hipStream_t s5, int rows) {
     const dim3 g5(tiles, rows, njobs);
     const int nb = std::max(c.beta(Lmax), 2);  // slots for the launch's own largest digit count
-    if (tiles * rows * njobs <= c.sched.small_grid && nb <= 4) {  // too few work-groups to fill the CUs
+    if (tiles * rows * njobs <= sc.small_grid && nb <= 4) {  // too few work-groups to fill the CUs
       // eighth tiles (radix-4 phases) while eight times the work-groups still
       // fit one per CU, else quarter tiles while four times do
       if (8 * tiles * rows * njobs <= 256) {
@@ -1240,7 +1242,8 @@ hipError_t ks_launch_t(const Ctx& c, const KsConst& K, const JobArg<KsJob>& jobs
   }
   if (split && (e = hipEventRecord(sp.join, sp.side)) != hipSuccess) return e;
   col_launch<K6c, L1>(c, CKKS_STAGE_INTT_COLS_P, 2 * c.k, njobs, true, st, K, jobs);
-  e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups);
+  e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups,
+                            down_rows);
   if (e != hipSuccess) return e;
   col_launch<K8c, L1>(c, CKKS_STAGE_NTT_COLS_DOWN, 2 * Lmax, njobs, false, st, K, jobs);
   if (split && (e = hipStreamWaitEvent(st, sp.join, 0)) != hipSuccess) return e;
@@ -1268,16 +1271,16 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
 }
 }  // namespace
 
-hipError_t ks_launch(const Ctx& c, const JobArg<KsJob>& jobs, int njobs, int Lmax, bool with_modup,
-                     bool with_hoist, hipStream_t st, const KsSplit& sp) {
+hipError_t ks_launch(const Ctx& c, const Ctx::Sched& sc, const JobArg<KsJob>& jobs, int njobs, int Lmax,
+                     bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp) {
   if (njobs <= 0) return hipSuccess;
   const KsConst K = make_const(c);
   switch (c.logN - kBlockLog) {
-    case 4: return ks_launch_t<4>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
-    case 5: return ks_launch_t<5>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
-    case 6: return ks_launch_t<6>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
-    case 7: return ks_launch_t<7>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
-    case 8: return ks_launch_t<8>(c, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 4: return ks_launch_t<4>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 5: return ks_launch_t<5>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 6: return ks_launch_t<6>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 7: return ks_launch_t<7>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    case 8: return ks_launch_t<8>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
     default: return hipErrorInvalidValue;
   }
 }

@@ -214,7 +214,7 @@ struct ckks_server {
     if (e == hipSuccess && nks) {
       JobArg<KsJob> ka{};
       ka.table = d_ks[ring];
-      e = ks_launch(c, ka, nks, Lks, true, false, st);
+      e = ks_launch(c, c.sched, ka, nks, Lks, true, false, st);
     }
     if (e == hipSuccess && nrs) {
       JobArg<RsJob> ra{};

@@ -134,7 +134,8 @@ def _check_plans(use_graph, plans):
         plan, us = P.ckks_batch_tune(b, reps=1)
         assert us > 0 and plan == P.ckks_batch_get_plan(b)
         log = P.ckks_batch_tune_log(b)
-        assert len(log) >= 3 and min(t for _, t in log) == us and (plan, us) in log
+        # the log holds the plan search; the schedule pass after it may only improve on it
+        assert len(log) >= 3 and us <= min(t for _, t in log) and plan in [p for p, _ in log]
         for j in jobs:
             j["out"].fill_(-1)
         P.ckks_batch_launch(b)
@@ -155,6 +156,50 @@ def test_graph_plans_give_the_single_call_results():
 def test_eager_plans_give_the_single_call_results():
     """Eager batches may also spread launch groups over concurrent branches."""
     _check_plans(False, [(0, 1, 0), (0, 2, 1), (1, 4, 2), (2, 3, 0), (3, 2, 1), (8, 1, 2)])
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_schedules_give_the_single_call_results(use_graph):
+    """A batch's own kernel schedule (and the one its tuner picks) changes only
+    launch shapes: every schedule reproduces the single calls bitwise, and the
+    context's schedule is left as it was."""
+    spec = ci.get("n16_l36")
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(spec.seed + 300)
+    keys = [dev(rng.evk(spec)) for _ in range(2)]
+    n = 9
+    levels = rng.integers(1, spec.L_max + 1, n)
+    jobs, singles = _make_jobs(spec, ctx, rng, n, levels, keys)
+    want = [_single(ctx, *s) for s in singles]
+    before = P.ckks_ctx_get_schedule(ctx.handle)
+    b = P.ckks_batch_create(ctx.handle, jobs, use_graph=use_graph)
+    try:
+        assert P.ckks_batch_get_schedule(b) == before
+        for sch in [(2, 12, 0), (12, 2, 65535), (6, 4, 128)]:
+            print(f"schedule {sch} graph={use_graph}", flush=True)
+            P.ckks_batch_set_schedule(b, *sch)
+            assert P.ckks_batch_get_schedule(b) == dict(zip(("bconv_up_rows", "bconv_down_rows", "small_grid"), sch))
+            for j in jobs:
+                j["out"].fill_(-1)
+            P.ckks_batch_launch(b)
+            torch.cuda.synchronize()
+            for i, j in enumerate(jobs):
+                msg = first_mismatch(host(j["out"]), want[i])
+                assert not msg, f"schedule {sch}, job {i} ({singles[i][0]}, L={singles[i][1]}): {msg}"
+        with pytest.raises(P.CkksError):
+            P.ckks_batch_set_schedule(b, 5, 6, 128)
+        P.ckks_batch_tune(b, reps=1)
+        tuned = P.ckks_batch_get_schedule(b)
+        for j in jobs:
+            j["out"].fill_(-1)
+        P.ckks_batch_launch(b)
+        torch.cuda.synchronize()
+        for i, j in enumerate(jobs):
+            msg = first_mismatch(host(j["out"]), want[i])
+            assert not msg, f"tuned schedule {tuned}, job {i}: {msg}"
+        assert P.ckks_ctx_get_schedule(ctx.handle) == before
+    finally:
+        P.ckks_batch_destroy(b)
 
 
 def test_graph_batch_rejects_several_branches():
