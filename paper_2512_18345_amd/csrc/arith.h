@@ -82,6 +82,12 @@ __device__ __forceinline__ uint4 ld4(const uint32_t* p) {
   const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)p;
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+// Streaming load: the non-temporal hint marks the line for early eviction
+// (data read once, such as evaluation-key words).
+__device__ __forceinline__ uint4 ld4nt(const uint32_t* p) {
+  const u32x4 v = __builtin_nontemporal_load((const __attribute__((address_space(1))) u32x4*)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
 __device__ __forceinline__ void st4(uint32_t* p, uint4 v) {
   const u32x4 w = {v.x, v.y, v.z, v.w};
   *(__attribute__((address_space(1))) u32x4*)p = w;
