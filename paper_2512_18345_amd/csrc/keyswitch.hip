@@ -268,7 +268,8 @@ __global__ __launch_bounds__(T) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) {
 // Stage 2: NTT block pass + inner product (+ first INTT pass of ModDown on P rows)
 // ============================================================================
 // HOIST selects the variant for hoisted-rotation jobs (gather of sigma(M), no
-// transform); the other variant serves every other job kind.
+// transform; each rotation brings its own key, streamed with the
+// non-temporal hint); the other variant serves every other job kind.
 template <int LOGN1, bool HOIST>
 __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> JA, int part) {
   const KsJob J = JA.get(blockIdx.z);
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
     const uint32_t* k1 = k0 + KR * N;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const uint4 e0 = ld4(k0 + blk_elem(kk));
+      const uint4 e0 = HOIST ? ld4nt(k0 + blk_elem(kk)) : ld4(k0 + blk_elem(kk));
       a0[4 * kk + 0] += (uint64_t)v[kk].x * e0.x;
       a0[4 * kk + 1] += (uint64_t)v[kk].y * e0.y;
       a0[4 * kk + 2] += (uint64_t)v[kk].z * e0.z;
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const uint4 e1 = ld4(k1 + blk_elem(kk));
+      const uint4 e1 = HOIST ? ld4nt(k1 + blk_elem(kk)) : ld4(k1 + blk_elem(kk));
       a1[4 * kk + 0] += (uint64_t)v[kk].x * e1.x;
       a1[4 * kk + 1] += (uint64_t)v[kk].y * e1.y;
       a1[4 * kk + 2] += (uint64_t)v[kk].z * e1.z;
