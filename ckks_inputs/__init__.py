@@ -32,6 +32,9 @@ __all__ = [
     "chain_spec",
     "CONFIGS",
     "Rng",
+    "batch_jobs",
+    "edge_residues",
+    "edge_evk",
 ]
 
 
@@ -173,3 +176,59 @@ class Rng:
 
     def integers(self, lo: int, hi: int, size=None):
         return self.g.integers(lo, hi, size)
+
+
+# The mixed-level batch at N=2^16: 64 jobs, levels uniform in 4..36, each an
+# HMult (probability 0.4, one relinearisation key), an HRot (0.4, rotation
+# 1..8, each rotation with its own key) or a rescale (0.2).
+BATCH_JOBS = 64
+BATCH_ROT_KEYS = 8
+
+
+def batch_jobs(spec: ChainSpec, seed: int = 3, n: int = BATCH_JOBS):
+    """Draw the mixed-level batch.  Returns (keys, jobs): keys[0..7] are the
+    rotation keys of rotations 1..8, keys[8] the relinearisation key; each job
+    is a dict with op ("HMULT" / "HROT" / "RESCALE"), L, rot, key (an index
+    into keys, None for rescale), in0 [2][L][N] and in1 (HMult only)."""
+    rng = Rng(seed)
+    keys = [rng.evk(spec) for _ in range(BATCH_ROT_KEYS + 1)]
+    jobs = []
+    for _ in range(n):
+        L = int(rng.integers(4, 37))
+        u = float(rng.integers(0, 10)) / 10.0
+        a = rng.polys(2, spec.q[:L], spec.N)
+        if u < 0.4:
+            b = rng.polys(2, spec.q[:L], spec.N)
+            jobs.append(dict(op="HMULT", L=L, rot=0, key=BATCH_ROT_KEYS, in0=a, in1=b))
+        elif u < 0.8:
+            r = int(rng.integers(0, BATCH_ROT_KEYS))
+            jobs.append(dict(op="HROT", L=L, rot=1 + r, key=r, in0=a, in1=None))
+        else:
+            jobs.append(dict(op="RESCALE", L=L, rot=0, key=None, in0=a, in1=None))
+    return keys, jobs
+
+
+EDGE_KINDS = ("max", "zero", "one_hot")
+
+
+def edge_residues(kind: str, primes: Sequence[int], N: int, pos: int = 0) -> np.ndarray:
+    """Extreme inputs [len(primes)][N]: "max" = every residue q_i - 1 (the
+    largest canonical word, which drives every product and lazy sum to its
+    bound), "zero" = all 0, "one_hot" = q_i - 1 at coefficient pos and 0
+    elsewhere."""
+    out = np.zeros((len(primes), N), dtype=np.uint32)
+    for i, q in enumerate(primes):
+        if kind == "max":
+            out[i] = q - 1
+        elif kind == "one_hot":
+            out[i, pos] = q - 1
+        elif kind != "zero":
+            raise ValueError(kind)
+    return out
+
+
+def edge_evk(kind: str, spec: ChainSpec, pos: int = 0) -> np.ndarray:
+    """An evaluation key [beta_max][2][L_max + k][N] of one extreme kind."""
+    rows = list(spec.q) + list(spec.p)
+    one = edge_residues(kind, rows, spec.N, pos)
+    return np.ascontiguousarray(np.broadcast_to(one, (spec.beta(spec.L_max), 2) + one.shape))

@@ -197,9 +197,11 @@ int ckks_hmult(const ckks_ctx *ctx, const uint32_t *ct1, const uint32_t *ct2, in
                const uint32_t *rlk, uint32_t *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
- * HRot by `rot` slots (left), g = 5^rot mod 2N: out = (sigma(c0) +
- * KS_0(sigma(c1)), KS_1(sigma(c1))).  rotk must switch sigma_g(s) -> s; the
- * library cannot check that.  ct, out: [2][L][N].
+ * HRot by `rot` slots (left), g = 5^rot mod 2N: the automorphism sigma_g of
+ * Sec. II-B3 (a column permutation of every limb) applied to both
+ * components, then the key-switching of Fig. keysw on the permuted c1:
+ * out = (sigma(c0) + KS_0(sigma(c1)), KS_1(sigma(c1))).  rotk must switch
+ * sigma_g(s) -> s; the library cannot check that.  ct, out: [2][L][N].
  */
 int ckks_hrot(const ckks_ctx *ctx, const uint32_t *ct, int L, int rot, const uint32_t *rotk,
               uint32_t *out, void *ws, size_t ws_bytes, void *stream);
@@ -218,9 +220,12 @@ int ckks_hrot_hoisted(const ckks_ctx *ctx, const uint32_t *ct, int L, const int 
                       size_t ws_bytes, void *stream);
 
 /*
- * Rescale by the top prime (drop q_{L-1}): for each component,
- * t = INTT_{q_{L-1}}(a_{L-1}); out_i = (a_i - NTT_{q_i}(t mod q_i)) * q_{L-1}^-1,
- * floor form.  ct: [2][L][N] -> out: [2][L-1][N]; L >= 2.
+ * Rescale by the top prime (drop q_{L-1}), the division by the scale factor
+ * that follows a multiplication (Sec. II-A: a ciphertext at level L holds L
+ * limbs; Table I's Delta is the scale kept by dropping limbs).  For each
+ * component, t = INTT_{q_{L-1}}(a_{L-1}); out_i = (a_i - NTT_{q_i}(t mod q_i))
+ * * q_{L-1}^-1 mod q_i, floor form (no rounding offset).
+ * ct: [2][L][N] -> out: [2][L-1][N]; 2 <= L <= L_max.
  */
 int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, void *ws,
                  size_t ws_bytes, void *stream);
@@ -327,13 +332,15 @@ typedef struct ckks_batch_plan {
 int ckks_batch_get_plan(const ckks_batch *batch, ckks_batch_plan *plan);
 /* Replace the plan (re-captures the graph of a graph batch).  Must not
  * overlap a launch of the same batch.  Errors: CKKS_EINVAL (bad plan),
- * CKKS_EUNSUPPORTED (streams > 1 on a graph batch), CKKS_EHIP. */
+ * CKKS_EUNSUPPORTED (streams > 1 on a graph batch), CKKS_EHIP.  On error the
+ * batch keeps its previous plan and graph. */
 int ckks_batch_set_plan(ckks_batch *batch, const ckks_batch_plan *plan);
 /*
  * A batch's own kernel schedule (struct ckks_schedule above): the context's
  * at creation; set here or by ckks_batch_tune.  Setting re-captures the
  * graph of a graph batch and must not overlap a launch of the same batch.
- * Errors: CKKS_EINVAL (bad schedule, as for ckks_ctx_set_schedule), CKKS_EHIP.
+ * Errors: CKKS_EINVAL (bad schedule, as for ckks_ctx_set_schedule), CKKS_EHIP;
+ * on error the batch keeps its previous schedule and graph.
  */
 int ckks_batch_get_schedule(const ckks_batch *batch, ckks_schedule *sched);
 int ckks_batch_set_schedule(ckks_batch *batch, const ckks_schedule *sched);
@@ -377,9 +384,18 @@ int ckks_batch_destroy(ckks_batch *batch);
  * slots and memory free up and their work overlaps on the device.  A job's
  * result is bitwise the same as in a single call.  Inputs, keys and outputs
  * are caller-owned device buffers that must stay valid until the ticket is
- * done.  A job whose scratch alone exceeds the budget is refused with
- * CKKS_ENOMEM.  Latencies are host wall-clock from submit to the worker
- * observing completion.
+ * done.  Ordering: ckks_server_submit records an event on `stream` (the
+ * stream on which the caller produced the job's inputs or last used its
+ * output buffer; NULL = the null stream), and the job's kernels start only
+ * after that event, so work the caller queued there before the submit is
+ * complete first.  Work queued on other streams is not waited for.
+ * The budget bounds the device memory the server itself takes: the scratch
+ * of the jobs on the device (ckks_workspace_bytes of the job's operation).
+ * Inputs, keys and outputs are not counted: the caller allocated them before
+ * the submit, so admitting a job does not change their footprint (keys are
+ * typically shared by many jobs).  A job whose scratch alone exceeds the
+ * budget is refused with CKKS_ENOMEM.  Latencies are host wall-clock from
+ * submit to the worker observing completion.
  */
 typedef struct ckks_server ckks_server;
 
@@ -392,7 +408,8 @@ typedef struct ckks_stats {
 
 int ckks_server_create(const ckks_ctx *const *ctxs, int nctx, size_t hbm_budget, int max_slots,
                        ckks_server **out);
-int ckks_server_submit(ckks_server *server, int ctx_index, const ckks_job *job, uint64_t *ticket);
+int ckks_server_submit(ckks_server *server, int ctx_index, const ckks_job *job, void *stream,
+                       uint64_t *ticket);
 /* *done = 1 once the ticket's result is in its output buffer. */
 int ckks_server_poll(ckks_server *server, uint64_t ticket, int *done);
 /* Block until every submitted job has completed. */

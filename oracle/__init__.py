@@ -59,11 +59,17 @@ def _lib():
     lib.oracle_intt.argtypes = [p32, ctypes.c_int, ctypes.c_int, p32, p32, p32]
     lib.oracle_bconv.argtypes = [p32, ctypes.c_int, p32, p32, p32, ctypes.c_int, p32, p32, ctypes.c_int]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     return lib
 
 
 def num_threads() -> int:
     return int(_lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the C row loops (timing only; results do not depend on it)."""
+    _lib().oracle_set_num_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

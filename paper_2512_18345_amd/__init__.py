@@ -119,7 +119,7 @@ _SIGS = {
     "ckks_pmult_sum": [_vp, _vp, _vp, _i, _i, _vp, _vp],
     "ckks_add": [_vp, _vp, _vp, _i, _vp, _vp],
     "ckks_server_create": [_vp, _i, _sz, _i, ctypes.POINTER(_vp)],
-    "ckks_server_submit": [_vp, _i, _vp, ctypes.POINTER(ctypes.c_uint64)],
+    "ckks_server_submit": [_vp, _i, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
     "ckks_server_poll": [_vp, ctypes.c_uint64, ctypes.POINTER(_i)],
     "ckks_server_drain": [_vp],
     "ckks_server_stats": [_vp, _vp],
@@ -379,11 +379,12 @@ def ckks_server_create(ctxs, hbm_budget, max_slots) -> int:
     return h.value
 
 
-def ckks_server_submit(server, ctx_index, job) -> int:
+def ckks_server_submit(server, ctx_index, job, stream=None) -> int:
+    """stream: where the job's inputs were produced (default: torch's current stream)."""
     j = _job(job)
     t = ctypes.c_uint64(0)
     _check(lib().ckks_server_submit(server, int(ctx_index), ctypes.cast(ctypes.byref(j), _vp),
-                                    ctypes.byref(t)))
+                                    _stream(stream), ctypes.byref(t)))
     return t.value
 
 

@@ -8,6 +8,7 @@ disabled for all device code.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -34,6 +35,7 @@ def sources():
 def build(verbose: bool = False) -> str:
     objs = []
     with tempfile.TemporaryDirectory(prefix="ckks_build_") as tmp:
+        cmds = []
         for src in sources():
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
             cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
@@ -41,8 +43,12 @@ def build(verbose: bool = False) -> str:
                 cmd[1:1] = ["-x", "hip"]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            subprocess.check_call(cmd)
+            cmds.append(cmd)
             objs.append(obj)
+        # one compiler process per source file, side by side
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as pool:
+            for f in [pool.submit(subprocess.check_call, cmd) for cmd in cmds]:
+                f.result()
         out_tmp = LIB + ".tmp"
         cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", out_tmp, *objs]
         if verbose:

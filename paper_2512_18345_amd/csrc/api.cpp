@@ -267,15 +267,26 @@ void batch_drop_graph(ckks_batch* b) {
   b->graph = nullptr;
 }
 
+// Capture the batch's launch sequence under its current plan and schedule.
+// The new graph replaces the old one only once it is instantiated; on failure
+// the batch keeps the graph it had.
 hipError_t batch_capture(ckks_batch* b) {
-  batch_drop_graph(b);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   const hipError_t le = batch_enqueue(b, b->capture);
-  e = hipStreamEndCapture(b->capture, &b->graph);
+  e = hipStreamEndCapture(b->capture, &graph);
   if (le != hipSuccess) e = le;
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-  return e;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return e;
+  }
+  batch_drop_graph(b);
+  b->graph = graph;
+  b->exec = exec;
+  return hipSuccess;
 }
 
 void batch_free(ckks_batch* b) {
@@ -731,10 +742,12 @@ int ckks_batch_launch(ckks_batch* b, void* stream) {
   if (!b) return fail(CKKS_EINVAL, "null batch");
   DeviceGuard g(b->c->device);
   const hipStream_t st = (hipStream_t)stream;
-  if (b->exec)
+  if (b->use_graph) {
+    if (!b->exec) return fail(CKKS_EHIP, "the batch has no instantiated graph");
     CKKS_TRY(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
-  else
+  } else {
     CKKS_TRY(batch_enqueue(b, st), "batch launch");
+  }
   return CKKS_OK;
 }
 
@@ -752,9 +765,16 @@ int ckks_batch_set_plan(ckks_batch* b, const ckks_batch_plan* plan) {
     return fail(CKKS_EUNSUPPORTED, "a graph batch runs one branch (streams = 1)");
   DeviceGuard g(b->c->device);
   CKKS_TRY(batch_events(b, *plan), "creating the batch's events");
+  const ckks_batch_plan old = b->plan;
   b->plan = *plan;
   b->plan.reserved = 0;
-  if (b->use_graph) CKKS_TRY(batch_capture(b), "re-capturing the batch graph");
+  if (b->use_graph) {
+    const hipError_t e = batch_capture(b);
+    if (e != hipSuccess) {
+      b->plan = old;  // the old graph is still in place
+      return hip_fail(e, "re-capturing the batch graph");
+    }
+  }
   return CKKS_OK;
 }
 
@@ -769,8 +789,15 @@ int ckks_batch_set_schedule(ckks_batch* b, const ckks_schedule* sched) {
   if (!sched_ok(*sched))
     return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12} and 0 <= small_grid <= 65535");
   DeviceGuard g(b->c->device);
+  const Ctx::Sched old = b->sched;
   b->sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid};
-  if (b->use_graph) CKKS_TRY(batch_capture(b), "re-capturing the batch graph");
+  if (b->use_graph) {
+    const hipError_t e = batch_capture(b);
+    if (e != hipSuccess) {
+      b->sched = old;  // the old graph is still in place
+      return hip_fail(e, "re-capturing the batch graph");
+    }
+  }
   return CKKS_OK;
 }
 
@@ -791,7 +818,7 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
   // (re-captured first for a graph batch); microseconds per launch
   auto time_it = [&](float* us) -> hipError_t {
     hipError_t te = b->use_graph ? batch_capture(b) : hipSuccess;
-    auto launch = [&]() { return b->exec ? hipGraphLaunch(b->exec, st) : batch_enqueue(b, st); };
+    auto launch = [&]() { return b->use_graph ? hipGraphLaunch(b->exec, st) : batch_enqueue(b, st); };
     if (te == hipSuccess) te = launch();
     if (te == hipSuccess) te = hipEventRecord(t0, st);
     for (int r = 0; r < reps && te == hipSuccess; ++r) te = launch();

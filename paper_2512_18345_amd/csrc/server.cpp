@@ -95,6 +95,8 @@ struct Req {
   int ctx;
   ckks_job job;
   size_t bytes;
+  hipEvent_t ready;  // recorded on the submitter's stream: the job's inputs are written
+  void* src;         // that stream
 };
 
 struct Flight {
@@ -102,6 +104,8 @@ struct Flight {
   int stream;
   hipEvent_t ev;
   std::vector<uint64_t> tickets;
+  // the jobs' submit events and streams (until the waits are enqueued)
+  std::vector<std::pair<void*, hipEvent_t>> ready;
   std::vector<std::pair<size_t, size_t>> allocs;
   int ks_jobs;
 };
@@ -134,6 +138,12 @@ struct ckks_server {
 
   std::deque<Req> pending;
   std::deque<Flight> inflight;
+  // Events that order a job after the work its submitter queued before it
+  // (recorded by ckks_server_submit on the submitter's stream, waited on by
+  // the batch's stream before the job-table copy).  Returned to the pool once
+  // the wait is enqueued: a later record does not affect an enqueued wait.
+  std::vector<hipEvent_t> event_pool;
+  std::vector<hipEvent_t> all_events;
   int jobs_on_device = 0;
   uint64_t next_ticket = 0;
   std::vector<double> t_submit, t_done;  // by ticket; t_done < 0 while pending
@@ -201,6 +211,7 @@ struct ckks_server {
       }
       f.tickets.push_back(r.ticket);
       f.allocs.emplace_back(off, r.bytes);
+      f.ready.emplace_back(r.src, r.ready);
       pending.pop_front();
     }
     if (f.tickets.empty()) return false;
@@ -208,7 +219,16 @@ struct ckks_server {
     f.stream = next_stream;
     next_stream = (next_stream + 1) % kStreams;
     hipError_t e = hipSuccess;
-    if (nks) e = hipMemcpyAsync(d_ks[ring], h_ks[ring], sizeof(KsJob) * nks, hipMemcpyHostToDevice, st);
+    // per submitting stream, the event of its last job in the batch covers the
+    // earlier ones (recorded in submit order on that stream)
+    for (size_t i = 0; i < f.ready.size() && e == hipSuccess; ++i) {
+      bool later = false;
+      for (size_t k = i + 1; k < f.ready.size(); ++k) later = later || f.ready[k].first == f.ready[i].first;
+      if (!later) e = hipStreamWaitEvent(st, f.ready[i].second, 0);
+    }
+    for (auto& rv : f.ready) event_pool.push_back(rv.second);
+    f.ready.clear();
+    if (e == hipSuccess && nks) e = hipMemcpyAsync(d_ks[ring], h_ks[ring], sizeof(KsJob) * nks, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nrs)
       e = hipMemcpyAsync(d_rs[ring], h_rs[ring], sizeof(RsJob) * nrs, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nks) {
@@ -244,7 +264,10 @@ struct ckks_server {
       if (stop && pending.empty() && inflight.empty()) break;
       if (error && inflight.empty()) {
         // nothing can complete any more: fail the queue
-        for (Req& r : pending) t_done[r.ticket] = now_us(t0);
+        for (Req& r : pending) {
+          t_done[r.ticket] = now_us(t0);
+          event_pool.push_back(r.ready);
+        }
         pending.clear();
         cv_done.notify_all();
         if (stop) break;
@@ -274,6 +297,7 @@ void server_free(ckks_server* s) {
   }
   for (hipStream_t st : s->streams)
     if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : s->all_events) (void)hipEventDestroy(ev);
   if (s->d_arena) (void)hipFree(s->d_arena);
   delete s;
 }
@@ -333,7 +357,7 @@ int ckks_server_create(const ckks_ctx* const* ctxs, int nctx, size_t hbm_budget,
   return CKKS_OK;
 }
 
-int ckks_server_submit(ckks_server* s, int ctx_index, const ckks_job* job, uint64_t* ticket) {
+int ckks_server_submit(ckks_server* s, int ctx_index, const ckks_job* job, void* stream, uint64_t* ticket) {
   if (!s || !job || !ticket) return api_fail(CKKS_EINVAL, "null argument");
   if (ctx_index < 0 || ctx_index >= (int)s->ctxs.size()) return api_fail(CKKS_EINVAL, "bad context index");
   const Ctx& c = *s->ctxs[ctx_index];
@@ -350,11 +374,30 @@ int ckks_server_submit(ckks_server* s, int ctx_index, const ckks_job* job, uint6
     ++s->rejected;
     return api_fail(CKKS_ENOMEM, "job scratch exceeds the server's HBM budget");
   }
+  // order the job after the work queued so far on the submitter's stream
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != s->device && hipSetDevice(s->device) != hipSuccess)
+    return api_fail(CKKS_EHIP, "hipSetDevice failed");
+  hipEvent_t ready = nullptr;
+  hipError_t e = hipSuccess;
+  if (!s->event_pool.empty()) {
+    ready = s->event_pool.back();
+    s->event_pool.pop_back();
+  } else if ((e = hipEventCreateWithFlags(&ready, hipEventDisableTiming)) == hipSuccess) {
+    s->all_events.push_back(ready);
+  }
+  if (e == hipSuccess) e = hipEventRecord(ready, (hipStream_t)stream);
+  if (prev != s->device) (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    if (ready) s->event_pool.push_back(ready);
+    return api_fail(CKKS_EHIP, std::string("recording the submit event: ") + hipGetErrorString(e));
+  }
   const uint64_t tk = s->next_ticket++;
   s->t_submit.push_back(now_us(s->t0));
   s->t_done.push_back(-1.0);
   s->is_ks.push_back(j.op != CKKS_JOB_RESCALE);
-  s->pending.push_back(Req{tk, ctx_index, j, bytes});
+  s->pending.push_back(Req{tk, ctx_index, j, bytes, ready, stream});
   s->cv_work.notify_one();
   *ticket = tk;
   return CKKS_OK;

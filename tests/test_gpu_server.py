@@ -1,7 +1,9 @@
 """Serving loop: requests of mixed N (2^15, 2^16), level and operation are
 submitted over time while earlier ones run; every result must equal the
-result of the same job run alone (tolerance 0: the arithmetic is exact).
-Admission respects the HBM budget; oversize jobs are refused."""
+result of the same job run alone (tolerance 0: the arithmetic is exact), and
+a seeded sample equals the oracle.  Jobs wait for the work queued before
+them on the submitting stream.  Admission respects the HBM budget; oversize
+jobs are refused."""
 import random
 import time
 
@@ -10,6 +12,7 @@ import pytest
 import torch
 
 import ckks_inputs as ci
+import oracle as O
 import paper_2512_18345_amd as P
 from gpu_helpers import dev, empty, first_mismatch, host
 
@@ -65,8 +68,24 @@ def _random_jobs(contexts, n, seed):
     return jobs
 
 
+def _oracle(spec, job):
+    par = O.Params.from_spec(spec)
+    L, op = job["L"], job["op"]
+    a = host(job["in0"])
+    if op == P.JOB["RESCALE"]:
+        return O.rescale(par, a, L)
+    if op == P.JOB["KEYSWITCH"]:
+        return O.keyswitch(par, a, L, host(job["key"]))
+    if op == P.JOB["HMULT"]:
+        return O.hmult(par, a, host(job["in1"]), L, host(job["key"]))
+    return O.hrot(par, a, L, job["rot"], host(job["key"]))
+
+
 def test_results_alone_equal_results_in_the_mix(contexts):
-    jobs = _random_jobs(contexts, 40, seed=51)
+    """72 jobs of mixed N, level and operation, submitted over time: every
+    result equals the job run alone, and a seeded sample of 16 equals the
+    oracle."""
+    jobs = _random_jobs(contexts, 72, seed=51)
     srv = P.ckks_server_create([c.handle for _, c in contexts], 6 << 30, 24)
     try:
         rnd = random.Random(5)
@@ -86,6 +105,46 @@ def test_results_alone_equal_results_in_the_mix(contexts):
         want = _alone(contexts[ci_][1], job)
         msg = first_mismatch(host(job["out"]), want)
         assert not msg, f"request {i} (ctx {ci_}, op {job['op']}, L={job['L']}): {msg}"
+    sample = np.random.default_rng(52).choice(len(jobs), 16, replace=False)
+    for i in sorted(int(v) for v in sample):
+        ci_, job = jobs[i]
+        msg = first_mismatch(host(job["out"]), _oracle(contexts[ci_][0], job))
+        assert not msg, f"request {i} (ctx {ci_}, op {job['op']}, L={job['L']}) vs oracle: {msg}"
+
+
+def test_jobs_wait_for_the_submitting_stream(contexts):
+    """A job's input is written, and its output buffer filled, by work queued
+    on the caller's stream just before the submit (behind a long-running
+    kernel): the job must see the written input and its result must land
+    after the fill."""
+    spec, ctx = contexts[1]
+    L, N = 24, spec.N
+    rng = ci.Rng(61)
+    key = dev(rng.evk(spec))
+    src = [dev(rng.polys(2, spec.q[:L], N)) for _ in range(3)]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    srv = P.ckks_server_create([ctx.handle], 4 << 30, 8)
+    try:
+        jobs = []
+        with torch.cuda.stream(side):
+            for a in src:
+                inp = torch.zeros_like(a)
+                out = torch.empty((2, L, N), dtype=torch.int32, device="cuda")
+                torch.cuda._sleep(20_000_000)  # a bounded spin, about 10 ms
+                inp.copy_(a)
+                out.fill_(-1)
+                job = dict(op=P.JOB["HMULT"], L=L, in0=inp, in1=inp, key=key, out=out)
+                P.ckks_server_submit(srv, 0, job, side)
+                jobs.append(job)
+        P.ckks_server_drain(srv)
+        torch.cuda.synchronize()
+    finally:
+        P.ckks_server_destroy(srv)
+    for i, job in enumerate(jobs):
+        ref = dict(job, in0=src[i], in1=src[i])
+        msg = first_mismatch(host(job["out"]), _alone(ctx, ref))
+        assert not msg, f"job {i}: {msg}"
 
 
 def test_budget_limits_admission_and_refuses_oversize(contexts):

@@ -1,7 +1,8 @@
 """The bootstrapping-shaped operation trace (hoisted baby-step rotations,
 plaintext inner sums, giant-step rotations, rescales, a squaring chain) run
 through the C-ABI, checked bit-exact against the same composition of oracle
-steps.  Same shape and chain as the N=2^16 workload, on a 2^12 ring."""
+steps: at the workload's own size (N=2^16, 36 + 12 primes, dnum 3) and with
+the same shape and chain on a 2^12 ring."""
 import numpy as np
 import pytest
 import torch
@@ -10,35 +11,15 @@ import ckks_inputs as ci
 import oracle as O
 import paper_2512_18345_amd as P
 from paper_2512_18345_amd import trace
+from compose import oracle_trace
 from gpu_helpers import dev, first_mismatch, host
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 
-def oracle_trace(par, ct, L, shape, rotkeys, rlk, pts):
-    def lin(ct, L):
-        baby, giant = shape["baby"], shape["giant"]
-        rotated = O.hrot_hoisted(par, ct, L, baby, [rotkeys[r] for r in baby])
-        acc = None
-        for g, rg in enumerate(giant):
-            inner = O.pmult_sum(par, rotated, pts[g * len(baby):(g + 1) * len(baby)], L)
-            out = O.hrot(par, inner, L, rg, rotkeys[rg])
-            acc = out if acc is None else O.ct_add(par, acc, out, L)
-        return O.rescale(par, acc, L), L - 1
-
-    for _ in range(shape["levels"]):
-        ct, L = lin(ct, L)
-    for _ in range(shape["chain"]):
-        ct = O.rescale(par, O.hmult(par, ct, ct, L, rlk), L)
-        L -= 1
-    for _ in range(shape["levels"]):
-        ct, L = lin(ct, L)
-    return ct, L
-
-
-def test_boot_shaped_trace_matches_oracle():
-    spec = ci.get("boot_trace_n12")
+def _trace_case(name):
+    spec = ci.get(name)
     shape = ci.BOOT_TRACE
     par = O.Params.from_spec(spec)
     ctx = P.Context.from_spec(spec)
@@ -54,8 +35,19 @@ def test_boot_shaped_trace_matches_oracle():
     want, Lw = oracle_trace(par, ct, L, shape, keys, rlk, pts)
     assert Lg == Lw == L - 2 * shape["levels"] - shape["chain"]
     msg = first_mismatch(host(got), want)
-    assert not msg, msg
+    assert not msg, f"{name}: {msg}"
     assert trace.key_switches(shape) == 132
+
+
+def test_boot_shaped_trace_matches_oracle():
+    _trace_case("boot_trace_n12")
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_boot_shaped_trace_n16_matches_oracle():
+    """The workload itself: N=2^16, L 36 -> 18, 132 key-switches, 2^15 slots."""
+    _trace_case("boot_trace_n16")
 
 
 def test_pmult_sum_and_add_against_oracle():
