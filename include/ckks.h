@@ -197,6 +197,23 @@ int ckks_hmult(const ckks_ctx *ctx, const uint32_t *ct1, const uint32_t *ct2, in
                const uint32_t *rlk, uint32_t *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * ckks_hmult without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, layouts and result as ckks_hmult
+ * (bitwise); the key-switching scratch is a static 128 MiB device array that
+ * the library holds on each device it runs on until the process ends (its
+ * address is taken once per device by ckks_ctx_create).  Allocates nothing
+ * and needs no zeroed memory: every scratch word is written before it is
+ * read.  Returns CKKS_ENOMEM when ckks_workspace_bytes(ctx, CKKS_OP_HMULT, L)
+ * exceeds 128 MiB (N = 2^16 with L = 36, k = 12, dnum = 3 needs 102 MiB).
+ * All calls on one device share that device's scratch: calls that may
+ * overlap on one device (different streams, or different host threads
+ * without ordering) race and give wrong results; order them on one stream.
+ */
+int ckks_hmult_noalloc(const ckks_ctx *ctx, const uint32_t *ct1, const uint32_t *ct2, int L,
+                       const uint32_t *rlk, uint32_t *out, void *stream);
+
+/*
  * HRot by `rot` slots (left), g = 5^rot mod 2N: the automorphism sigma_g of
  * Sec. II-B3 (a column permutation of every limb) applied to both
  * components, then the key-switching of Fig. keysw on the permuted c1:

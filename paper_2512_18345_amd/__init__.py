@@ -16,7 +16,7 @@ __all__ = [
     "CkksError", "lib", "Context", "OP",
     "ckks_ctx_create", "ckks_ctx_destroy", "ckks_workspace_bytes",
     "ckks_ntt", "ckks_intt", "ckks_automorph", "ckks_tensor", "ckks_modup",
-    "ckks_inner_product", "ckks_moddown", "ckks_keyswitch", "ckks_hmult",
+    "ckks_inner_product", "ckks_moddown", "ckks_keyswitch", "ckks_hmult", "ckks_hmult_noalloc",
     "ckks_hrot", "ckks_hrot_hoisted", "ckks_rescale", "ckks_trace_begin", "ckks_trace_end", "STAGE",
     "JOB", "ckks_job", "ckks_batch_create", "ckks_batch_launch", "ckks_batch_device_bytes",
     "ckks_batch_destroy", "ckks_batch_plan", "ckks_batch_get_plan", "ckks_batch_set_plan",
@@ -100,6 +100,7 @@ _SIGS = {
     "ckks_moddown": [_vp, _vp, _i, _vp, _vp, _sz, _vp],
     "ckks_keyswitch": [_vp, _vp, _i, _vp, _vp, _vp, _sz, _vp],
     "ckks_hmult": [_vp, _vp, _vp, _i, _vp, _vp, _vp, _sz, _vp],
+    "ckks_hmult_noalloc": [_vp, _vp, _vp, _i, _vp, _vp, _vp],
     "ckks_hrot": [_vp, _vp, _i, _i, _vp, _vp, _vp, _sz, _vp],
     "ckks_hrot_hoisted": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _sz, _vp],
     "ckks_rescale": [_vp, _vp, _i, _vp, _vp, _sz, _vp],
@@ -240,6 +241,10 @@ def ckks_keyswitch(ctx, d, L, evk, out, ws=None, stream=None):
 def ckks_hmult(ctx, ct1, ct2, L, rlk, out, ws=None, stream=None):
     w, nb = _ws(ws)
     _check(lib().ckks_hmult(ctx, _ptr(ct1), _ptr(ct2), L, _ptr(rlk), _ptr(out), w, nb, _stream(stream)))
+
+
+def ckks_hmult_noalloc(ctx, ct1, ct2, L, rlk, out, stream=None):
+    _check(lib().ckks_hmult_noalloc(ctx, _ptr(ct1), _ptr(ct2), L, _ptr(rlk), _ptr(out), _stream(stream)))
 
 
 def ckks_hrot(ctx, ct, L, rot, rotk, out, ws=None, stream=None):

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,14 @@
 #include "kernels.h"
 
 using namespace ckks;
+
+// Key-switching scratch of ckks_hmult_noalloc, for callers that cannot
+// allocate: 128 MiB per device, enough for an HMult at N = 2^16 with L = 36,
+// k = 12, dnum = 3 (102 MiB).  Host code never uses the array's name as an
+// address: each device's copy is reached through the pointer that
+// hipGetSymbolAddress returns on that device (g_scratch_ptr).
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) uint32_t scratch[kScratchBytes / 4];
 
 namespace {
 
@@ -48,6 +57,29 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+// Device address of `scratch` on each device, set once per device by
+// ckks_ctx_create with that device current.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+int scratch_setup(int device) {
+  if (device >= kMaxScratchDevices) return 0;  // ckks_hmult_noalloc refuses such devices
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return 0;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+  g_scratch_ptr[device] = p;
+  return 0;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 constexpr size_t kAlign = 256;
 size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
@@ -332,6 +364,7 @@ int ckks_ctx_create(ckks_ctx** out, int logN, const uint32_t* h_q, int L_max, co
     return fail(CKKS_EINVAL, "no such HIP device");
   DeviceGuard g(device);
   if (!g.ok) return fail(CKKS_EHIP, "hipSetDevice failed");
+  if (const int rc = scratch_setup(device)) return rc;
   ckks_ctx* ctx = new (std::nothrow) ckks_ctx;
   if (!ctx) return fail(CKKS_ENOMEM, "host allocation failed");
   Ctx& c = ctx->c;
@@ -488,6 +521,23 @@ int ckks_hmult(const ckks_ctx* ctx, const uint32_t* ct1, const uint32_t* ct2, in
   if (!ct1 || !ct2 || !rlk || !out) return fail(CKKS_EINVAL, "null data pointer");
   const Ctx& c = ctx->c;
   if ((rc = check_ws(c, CKKS_OP_HMULT, L, ws, ws_bytes_given))) return rc;
+  DeviceGuard g(c.device);
+  return run_one(c, KS_HMULT, L, 0, ct1, ct2, rlk, out, ws, (hipStream_t)stream);
+}
+
+int ckks_hmult_noalloc(const ckks_ctx* ctx, const uint32_t* ct1, const uint32_t* ct2, int L,
+                       const uint32_t* rlk, uint32_t* out, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!ct1 || !ct2 || !rlk || !out) return fail(CKKS_EINVAL, "null data pointer");
+  const Ctx& c = ctx->c;
+  const size_t need = ws_bytes(c, CKKS_OP_HMULT, L);
+  if (need > kScratchBytes)
+    return fail(CKKS_ENOMEM, "HMult at L=" + std::to_string(L) + " needs " + std::to_string(need) +
+                                 " bytes of scratch; the static scratch holds " +
+                                 std::to_string(kScratchBytes));
+  void* ws = scratch_ptr(c.device);
+  if (!ws) return fail(CKKS_EUNSUPPORTED, "no static scratch on device " + std::to_string(c.device));
   DeviceGuard g(c.device);
   return run_one(c, KS_HMULT, L, 0, ct1, ct2, rlk, out, ws, (hipStream_t)stream);
 }
