@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uin
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   __shared__ uint2 stw[256];
-  stage_tw(stw, T.blk_tw(pi), 256);
+  stage_tw_perm(stw, T.blk_tw(pi));
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uin
                                 T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, stw, q, q2);
+  blk_stages<false>(s, PermTw{stw}, q, q2);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const ui
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   __shared__ uint2 stw[256];
-  stage_tw(stw, T.blk_itw(pi), 256);
+  stage_tw_perm(stw, T.blk_itw(pi));
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const ui
     lds_blk4_store(s, e, ld4(in + e));
   }
   __syncthreads();
-  blk_stages<true>(s, stw, q, q2);
+  blk_stages<true>(s, PermTw{stw}, q, q2);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {

@@ -139,7 +139,10 @@ __global__ __launch_bounds__(BPW * 256 / EPT) void k1_intt_blks(KsConst K, JobAr
   const ModC m = ldc(K.T.mod + r);
   const uint32_t q = m.q, q2 = 2 * q;
   __shared__ uint2 stw[256];
-  stage_tw(stw, K.T.blk_itw(r), 256);  // (T >= 256)
+  if constexpr (EPT == 16)  // (T >= 256)
+    stage_tw_perm(stw, K.T.blk_itw(r));
+  else
+    stage_tw(stw, K.T.blk_itw(r), 256);
   constexpr int T = BPW * 256 / EPT;  // threads
   constexpr int QPT = EPT / 4;        // quads per thread
   const int blk0 = blockIdx.x * BPW;
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(BPW * 256 / EPT) void k1_intt_blks(KsConst K, JobAr
   }
   __syncthreads();
   if constexpr (EPT == 16)
-    blk_stages<true>(s, stw, q, q2);
+    blk_stages<true>(s, PermTw{stw}, q, q2);
   else if constexpr (EPT == 8)
     blk_stages_r8<true, const uint2*, T>(s, stw, q, q2);
   else
@@ -281,8 +284,8 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
   __shared__ __align__(16) uint32_t s[kLds];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
   __shared__ uint2 stw[256], stwi[256];
-  stage_tw(stw, K.T.blk_tw(pi), 256);
-  if (r >= V.L) stage_tw(stwi, K.T.blk_itw(pi), 256);
+  stage_tw_perm(stw, K.T.blk_tw(pi));
+  if (r >= V.L) stage_tw_perm(stwi, K.T.blk_itw(pi));
   const ModC m = ldc(K.T.mod + pi);
   const uint32_t q = m.q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
                                     K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
       }
       __syncthreads();
-      blk_stages<false>(s, stw, q, q2);
+      blk_stages<false>(s, PermTw{stw}, q, q2);
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) v[kk] = canon4(lds_blk4(s, blk_elem(kk)), q, q2);
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
       lds_blk4_store(s, blk_elem(kk), make_uint4(rr[4 * kk], rr[4 * kk + 1], rr[4 * kk + 2], rr[4 * kk + 3]));
     }
     __syncthreads();
-    blk_stages<true>(s, stwi, q, q2);
+    blk_stages<true>(s, PermTw{stwi}, q, q2);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   // transforms issue no global load.  The key words of the first KPF quads
   // are requested now, after the digit loads: their latency overlaps the
   // transforms below (all four quads would cost a resident work-group).
-  stage_tw_pads(s, K.T.blk_tw(pi));
+  stage_tw_pads_perm(s, K.T.blk_tw(pi));
   constexpr int KPF = NB <= 2 ? 4 : 2;
   uint4 kpre0[KPF][NB], kpre1[KPF][NB];
   // (no branch here: a control-flow merge would make the compiler wait for
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   // The block-pass transforms of all digit tiles, phase by phase: the tiles
   // share the prime, so each phase's twiddles are fetched once for all of
   // them, and there are two barrier intervals instead of two per tile.
-  const PadTw tw{s};
+  const PadTwP tw{s};
 #pragma unroll
   for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll
@@ -528,15 +531,15 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   // inverse twiddles in the same pads (the forward ones were last read before
   // the barrier that ended the transforms)
   __syncthreads();
-  stage_tw_pads(s, K.T.blk_itw(pi));
+  stage_tw_pads_perm(s, K.T.blk_itw(pi));
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     lds_blk4_store(s, blk_elem(kk), res0[kk]);
     lds_blk4_store(s + kLds, blk_elem(kk), res1[kk]);
   }
   __syncthreads();
-  blk_stages<true>(s, PadTw{s}, q, q2);
-  blk_stages<true>(s + kLds, PadTw{s}, q, q2);
+  blk_stages<true>(s, PadTwP{s}, q, q2);
+  blk_stages<true>(s + kLds, PadTwP{s}, q, q2);
   __syncthreads();
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -604,7 +607,12 @@ __global__ __launch_bounds__((k5p_threads<BPW, EPT>())) void k5p_ntt_blks_ip(KsC
       }
     }
   }
-  if (threadIdx.x < 256) stage_tw_pads(s, K.T.blk_tw(pi), threadIdx.x);
+  if (threadIdx.x < 256) {
+    if constexpr (EPT == 16)
+      stage_tw_pads_perm(s, K.T.blk_tw(pi), threadIdx.x);
+    else
+      stage_tw_pads(s, K.T.blk_tw(pi), threadIdx.x);
+  }
   // key words of this thread's quad, requested before the transforms (the
   // first TQ threads form the inner product: all of them when EPT = 16)
   const bool ipt = EPT == 16 || (int)threadIdx.x < TQ;
@@ -619,9 +627,10 @@ __global__ __launch_bounds__((k5p_threads<BPW, EPT>())) void k5p_ntt_blks_ip(KsC
   __syncthreads();
   const PadTw tw{s};
   if constexpr (EPT == 16) {
-    if (have && !own) blk_phase<4, false>(s + grp * kLds, 4, tw, q, q2, lt);
+    const PadTwP twp{s};
+    if (have && !own) blk_phase<4, false>(s + grp * kLds, 4, twp, q, q2, lt);
     __syncthreads();
-    if (have && !own) blk_phase<4, false>(s + grp * kLds, 0, tw, q, q2, lt);
+    if (have && !own) blk_phase<4, false>(s + grp * kLds, 0, twp, q, q2, lt);
   } else {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -673,12 +682,17 @@ __global__ __launch_bounds__((k5p_threads<BPW, EPT>())) void k5p_ntt_blks_ip(KsC
     lds_blk4_store(s, e, res0);
     lds_blk4_store(s + kLds, e, res1);
   }
-  if (threadIdx.x < 256) stage_tw_pads(s, K.T.blk_itw(pi), threadIdx.x);
+  if (threadIdx.x < 256) {
+    if constexpr (EPT == 16)
+      stage_tw_pads_perm(s, K.T.blk_itw(pi), threadIdx.x);
+    else
+      stage_tw_pads(s, K.T.blk_itw(pi), threadIdx.x);
+  }
   __syncthreads();
   if constexpr (EPT == 16) {
-    if (grp < 2) blk_phase<4, true>(s + grp * kLds, 0, PadTw{s}, q, q2, lt);
+    if (grp < 2) blk_phase<4, true>(s + grp * kLds, 0, PadTwP{s}, q, q2, lt);
     __syncthreads();
-    if (grp < 2) blk_phase<4, true>(s + grp * kLds, 4, PadTw{s}, q, q2, lt);
+    if (grp < 2) blk_phase<4, true>(s + grp * kLds, 4, PadTwP{s}, q, q2, lt);
   } else {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -798,7 +812,10 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
   if (gr >= 2 * V.L) return;
   const int c = gr / V.L, i = gr % V.L;
   __shared__ uint2 stw[256];
-  stage_tw(stw, K.T.blk_tw(i), 256);
+  if constexpr (BPW == 16)
+    stage_tw_perm(stw, K.T.blk_tw(i));
+  else
+    stage_tw(stw, K.T.blk_tw(i), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const ModC m = ldc(K.T.mod + i);
   const uint32_t q = m.q, q2 = 2 * q;
@@ -814,7 +831,7 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
   }
   __syncthreads();
   if constexpr (BPW == 16)
-    blk_stages<false>(s, stw, q, q2);
+    blk_stages<false>(s, PermTw{stw}, q, q2);
   else
     blk_stages_r4<false, const uint2*, kWG>(s, stw, q, q2);
   __syncthreads();
@@ -880,7 +897,10 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, L = J.L, pi = L - 1;
   __shared__ uint2 stw[256];
-  stage_tw(stw, K.T.blk_itw(pi), 256);
+  if constexpr (BPW == 16)
+    stage_tw_perm(stw, K.T.blk_itw(pi));
+  else
+    stage_tw(stw, K.T.blk_itw(pi), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
@@ -895,7 +915,7 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
   }
   __syncthreads();
   if constexpr (BPW == 16)
-    blk_stages<true>(s, stw, q, q2);
+    blk_stages<true>(s, PermTw{stw}, q, q2);
   else
     blk_stages_r4<true, const uint2*, kWG>(s, stw, q, q2);
   __syncthreads();
@@ -978,7 +998,7 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
   __shared__ uint2 stw[256];
-  stage_tw(stw, K.T.blk_tw(i), 256);
+  stage_tw_perm(stw, K.T.blk_tw(i));
   __shared__ __align__(16) uint32_t s[kLds];
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
@@ -992,7 +1012,7 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
                                 K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
   __syncthreads();
-  blk_stages<false>(s, stw, q, q2);
+  blk_stages<false>(s, PermTw{stw}, q, q2);
   __syncthreads();
   const uint2 qi = ldc(K.rescale_inv + (size_t)J.L * K.T.L_max + i);
   const uint32_t* a = J.a + ((size_t)c * J.L + i) * N + base;

@@ -70,6 +70,55 @@ __device__ __forceinline__ void stage_tw_pads(uint32_t* s, const uint2* __restri
   s[lidx_pad(2 * tid + 1)] = w.y;
 }
 
+// Bank-conflict-free order of the block-pass table for the radix-16 phases.
+// In the second phase (stages on pos bits 3..0) a wave instruction reads, for
+// stage bit beta, the entries 2^(7-beta) + r 2^(3-beta) + c of the 16 values
+// r = line position / 16 of its lanes (c fixed by the instruction).  In
+// natural order those 16 entries sit 2^(4-beta) words apart and fall on 2,
+// 4 or 8 banks (up to eight-way conflicts); stored at slot 2^(7-beta) +
+// 16 c + r they are 16 consecutive entries.  Entries below 16 (the first
+// phase reads each of them from every lane at once) keep their place.
+__device__ __forceinline__ int tw_perm_slot(int beta, int x) {
+  if (beta >= 4) return (1 << (7 - beta)) | x;
+  const int lo = 3 - beta;
+  return (1 << (7 - beta)) + ((x & ((1 << lo) - 1)) << 4) + (x >> lo);
+}
+// The slot of entry i (1 <= i < 256) in that order.
+__device__ __forceinline__ int tw_perm_of(int i) {
+  const int beta = 7 - (31 - __clz(i));
+  return tw_perm_slot(beta, i - (1 << (7 - beta)));
+}
+// Pad-resident table in the conflict-free order (staged by stage_tw_pads_perm).
+struct PadTwP {
+  const uint32_t* s;
+  __device__ __forceinline__ uint2 at(int beta, int x) const {
+    const int u = 2 * tw_perm_slot(beta, x);
+    return make_uint2(s[lidx_pad(u)], s[lidx_pad(u + 1)]);
+  }
+};
+// Table in its own LDS array in the conflict-free order (staged by stage_tw_perm).
+struct PermTw {
+  const uint2* t;
+  __device__ __forceinline__ uint2 at(int beta, int x) const { return t[tw_perm_slot(beta, x)]; }
+};
+__device__ __forceinline__ void stage_tw_pads_perm(uint32_t* s, const uint2* __restrict__ tw,
+                                                   int tid = threadIdx.x) {
+  const uint2 w = tw[tid];
+  const int u = 2 * (tid ? tw_perm_of(tid) : 0);
+  s[lidx_pad(u)] = w.x;
+  s[lidx_pad(u + 1)] = w.y;
+}
+
+// Twiddle of the block-pass pair on pos bit beta (x = pos >> (beta + 1)).
+__device__ __forceinline__ uint2 blk_tw_at(const uint2* tw, int beta, int x) {
+  return tw[(1 << (7 - beta)) | x];
+}
+__device__ __forceinline__ uint2 blk_tw_at(const PadTw& tw, int beta, int x) {
+  return tw[(1 << (7 - beta)) | x];
+}
+__device__ __forceinline__ uint2 blk_tw_at(const PadTwP& tw, int beta, int x) { return tw.at(beta, x); }
+__device__ __forceinline__ uint2 blk_tw_at(const PermTw& tw, int beta, int x) { return tw.at(beta, x); }
+
 // ----- column-pass phases (stages on pos bits [blo, blo + LOGR)) -----------
 template <int LOGR, bool INV, int ELEMS, int T = kWG>
 __device__ __forceinline__ void col_phase(uint32_t* s, int logN1, int C, int blo,
@@ -151,7 +200,7 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, ui
             v[j | (1 << kb)] = xx + q2 - yy;
           } else {
             const int pos = base | (j << blo);
-            const uint2 W = tw[(1 << (7 - beta)) | (pos >> (beta + 1))];
+            const uint2 W = blk_tw_at(tw, beta, pos >> (beta + 1));
             bfly_ct(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
           }
         }
@@ -169,7 +218,7 @@ __device__ __forceinline__ void blk_phase(uint32_t* s, int blo, const TW& tw, ui
             v[j | (1 << kb)] = csub(x + q2 - y, q2);
           } else {
             const int pos = base | (j << blo);
-            const uint2 W = tw[(1 << (7 - beta)) | (pos >> (beta + 1))];
+            const uint2 W = blk_tw_at(tw, beta, pos >> (beta + 1));
             bfly_gs(v[j], v[j | (1 << kb)], W.x, W.y, q, q2);
           }
         }
@@ -307,6 +356,11 @@ __device__ __forceinline__ void col_quad(int k, int& pos, int& c) {
 // that no transform phase waits on a global load of its twiddles.
 __device__ __forceinline__ void stage_tw(uint2* stw, const uint2* __restrict__ tw, int n) {
   if ((int)threadIdx.x < n) stw[threadIdx.x] = tw[threadIdx.x];
+}
+// The 256-entry block-pass table in the conflict-free order of PermTw.
+__device__ __forceinline__ void stage_tw_perm(uint2* stw, const uint2* __restrict__ tw) {
+  const int t = threadIdx.x;
+  if (t < 256) stw[t ? tw_perm_of(t) : 0] = tw[t];
 }
 
 template <int LOGN1, int CW = 0, int T = kWG>
