@@ -336,7 +336,7 @@ int ckks_batch_launch(ckks_batch *batch, void *stream);
  * starts it beside the P-row inner product, split = 2 after it, so that it
  * overlaps only the P-row ModDown chain.
  * Rescale jobs run on the last branch.  Every plan gives bitwise the same
- * results.  Default {0, 1, 1}.  A batch created with use_graph runs one
+ * results.  Default {0, 1, 1}; {0, 1, 0} for a batch of one key-switching job.  A batch created with use_graph runs one
  * branch (streams = 1): a multi-branch launch sequence is not captured.
  */
 typedef struct ckks_batch_plan {

@@ -746,6 +746,9 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
   b->Lmax_rs = Lrs;
   b->use_graph = use_graph != 0;
   b->sched = ctx->c.sched;
+  // complementary pipelining pays off only when a launch group holds several
+  // jobs; a lone key-switch runs unsplit, as a single call does
+  b->plan.split = b->n_ks >= 2 ? 1 : 0;
   const size_t tab = round_up(sizeof(KsJob) * ks.size()) + round_up(sizeof(RsJob) * rs.size());
   if (hipMalloc(&b->d_ws, ws) != hipSuccess ||
       (!ks.empty() && hipMalloc(&b->d_ks, sizeof(KsJob) * ks.size()) != hipSuccess) ||

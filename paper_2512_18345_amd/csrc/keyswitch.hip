@@ -417,40 +417,39 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   const uint32_t base = blk0 * 256;
   const size_t KR = (size_t)K.T.L_max + K.k;  // key rows
 
-  // stage every digit's tile: the transformed ModUp row, or the digit row itself
+  // Every load of the staging is issued before any of them is used, in
+  // straight-line code (a branch between them would make the compiler wait
+  // for the earlier ones), in the order they are consumed (vmcnt counts in
+  // order): the block-pass twiddles for the pads of slots 0 and 1 (so the
+  // transforms issue no global load), the twist factors of the thread's
+  // quads (shared by all digits: they depend on the prime and the block),
+  // each digit's tile -- the digit row itself for the digit that holds r,
+  // else its ModUp row; digits past beta re-read the last digit's rows,
+  // unused -- and the key words of the first KPF quads, whose latency
+  // overlaps the transforms.
+  const uint2 tw_word = K.T.blk_tw(pi)[threadIdx.x];
+  Twist4 tf[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    tf[kk] = twist4_load(K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255);
+  }
+  uint4 raw[NB][4];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (j >= V.beta) break;
-    const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
-    uint32_t* slot = s + j * kLds;
-    if (r >= lo && r < hi) {
-      const uint32_t* drow = (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base;
+    const int jj = min(j, V.beta - 1);
+    const int lo = jj * K.alpha, hi = min(lo + K.alpha, V.L);
+    const uint32_t* src = (r >= lo && r < hi) ? (J.kind == KS_PLAIN ? J.a : V.de) + (size_t)r * N + base
+                                              : V.z + ((size_t)jj * V.R + r) * N + base;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int e = blk_elem(kk);
-        lds_blk4_store(slot, e, ld4(drow + e));
-      }
-    } else {
-      const uint32_t* zrow = V.z + ((size_t)j * V.R + r) * N + base;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int e = blk_elem(kk);
-        lds_blk4_store(slot, e, twist4(ld4(zrow + e),
-                                       K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
-      }
-    }
+    for (int kk = 0; kk < 4; ++kk) raw[j][kk] = ld4(src + blk_elem(kk));
   }
-  // The block-pass twiddles go to the pads of slots 0 and 1, so the
-  // transforms issue no global load.  The key words of the first KPF quads
-  // are requested now, after the digit loads: their latency overlaps the
-  // transforms below (all four quads would cost a resident work-group).
-  stage_tw_pads_perm(s, K.T.blk_tw(pi));
+  // The inner product loads the key words of the quads past KPF itself: a
+  // third prefetched quad of three digits takes the registers past what three
+  // resident work-groups per CU leave (171 VGPRs against 168).
   constexpr int KPF = NB <= 2 ? 4 : 2;
-  uint4 kpre0[KPF][NB], kpre1[KPF][NB];
-  // (no branch here: a control-flow merge would make the compiler wait for
-  // these loads; digits past beta re-read the last digit's rows, unused)
-#pragma unroll
-  for (int kk = 0; kk < KPF; ++kk)
+  uint4 kpre0[4][NB], kpre1[4][NB];
+  auto key_quad = [&](int kk) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int jj = min(j, V.beta - 1);
@@ -458,6 +457,24 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
       kpre0[kk][j] = NT ? ld4nt(k0) : ld4(k0);
       kpre1[kk][j] = NT ? ld4nt(k0 + KR * N) : ld4(k0 + KR * N);
     }
+  };
+#pragma unroll
+  for (int kk = 0; kk < KPF; ++kk) key_quad(kk);
+  stage_tw_pads_perm_word(s, tw_word);
+  // stage every digit's tile: the digit row as it is, a ModUp row twisted
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j >= V.beta) break;
+    const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
+    uint32_t* slot = s + j * kLds;
+    if (r >= lo && r < hi) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) lds_blk4_store(slot, blk_elem(kk), raw[j][kk]);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) lds_blk4_store(slot, blk_elem(kk), twist4(raw[j][kk], tf[kk], q));
+    }
+  }
   __syncthreads();
   // The block-pass transforms of all digit tiles, phase by phase: the tiles
   // share the prime, so each phase's twiddles are fetched once for all of
@@ -493,15 +510,12 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
       v.y &= msk;
       v.z &= msk;
       v.w &= msk;
-      uint4 e0, e1;
-      if (kk < KPF) {
-        e0 = kpre0[kk][j];
-        e1 = kpre1[kk][j];
-      } else {
+      if (kk >= KPF) {
         const uint32_t* k0 = J.key + ((size_t)min(j, V.beta - 1) * 2 * KR + pi) * N + base + e;
-        e0 = NT ? ld4nt(k0) : ld4(k0);
-        e1 = NT ? ld4nt(k0 + KR * N) : ld4(k0 + KR * N);
+        kpre0[kk][j] = NT ? ld4nt(k0) : ld4(k0);
+        kpre1[kk][j] = NT ? ld4nt(k0 + KR * N) : ld4(k0 + KR * N);
       }
+      const uint4 e0 = kpre0[kk][j], e1 = kpre1[kk][j];
       a0[0] += (uint64_t)v.x * e0.x;
       a0[1] += (uint64_t)v.y * e0.y;
       a0[2] += (uint64_t)v.z * e0.z;
@@ -529,7 +543,14 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   }
   // P rows: the INTT block pass of ModDown on both components (slots 0 and 1),
   // inverse twiddles in the same pads (the forward ones were last read before
-  // the barrier that ended the transforms)
+  // the barrier that ended the transforms); the inverse twist factors are
+  // requested first, so their latency overlaps the transforms
+  Twist4 tfi[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    tfi[kk] = twist4_load(K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255);
+  }
   __syncthreads();
   stage_tw_pads_perm(s, K.T.blk_itw(pi));
 #pragma unroll
@@ -544,9 +565,8 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int e = blk_elem(kk);
-    const uint2* tb = K.T.blk_itwist(pi, blk0 + (e >> 8));
-    st4(acc0 + e, twist4(lds_blk4(s, e), tb, e & 255, q));
-    st4(acc1 + e, twist4(lds_blk4(s + kLds, e), tb, e & 255, q));
+    st4(acc0 + e, twist4(lds_blk4(s, e), tfi[kk], q));
+    st4(acc1 + e, twist4(lds_blk4(s + kLds, e), tfi[kk], q));
   }
 }
 

@@ -109,6 +109,13 @@ __device__ __forceinline__ void stage_tw_pads_perm(uint32_t* s, const uint2* __r
   s[lidx_pad(u + 1)] = w.y;
 }
 
+// The same, from the entry of this thread already loaded (tw[tid]).
+__device__ __forceinline__ void stage_tw_pads_perm_word(uint32_t* s, uint2 w, int tid = threadIdx.x) {
+  const int u = 2 * (tid ? tw_perm_of(tid) : 0);
+  s[lidx_pad(u)] = w.x;
+  s[lidx_pad(u + 1)] = w.y;
+}
+
 // Twiddle of the block-pass pair on pos bit beta (x = pos >> (beta + 1)).
 __device__ __forceinline__ uint2 blk_tw_at(const uint2* tw, int beta, int x) {
   return tw[(1 << (7 - beta)) | x];
@@ -338,6 +345,26 @@ __device__ __forceinline__ uint4 twist4(uint4 v, const uint2* __restrict__ tb, i
   v.y = mul_shoup(mul_shoup(v.y, l1.x, l1.y, q), hi.x, hi.y, q);
   v.z = mul_shoup(mul_shoup(v.z, l2.x, l2.y, q), hi.x, hi.y, q);
   v.w = mul_shoup(mul_shoup(v.w, l3.x, l3.y, q), hi.x, hi.y, q);
+  return v;
+}
+
+// The factors twist4 reads for the quad at block position pos, loaded ahead
+// (they depend on the prime and the block only, so tiles of one row share them).
+struct Twist4 {
+  uint2 lo[4], hi;
+};
+__device__ __forceinline__ Twist4 twist4_load(const uint2* __restrict__ tb, int pos) {
+  Twist4 t;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t.lo[i] = tb[(pos & 15) + i];
+  t.hi = tb[16 + (pos >> 4)];
+  return t;
+}
+__device__ __forceinline__ uint4 twist4(uint4 v, const Twist4& t, uint32_t q) {
+  v.x = mul_shoup(mul_shoup(v.x, t.lo[0].x, t.lo[0].y, q), t.hi.x, t.hi.y, q);
+  v.y = mul_shoup(mul_shoup(v.y, t.lo[1].x, t.lo[1].y, q), t.hi.x, t.hi.y, q);
+  v.z = mul_shoup(mul_shoup(v.z, t.lo[2].x, t.lo[2].y, q), t.hi.x, t.hi.y, q);
+  v.w = mul_shoup(mul_shoup(v.w, t.lo[3].x, t.lo[3].y, q), t.hi.x, t.hi.y, q);
   return v;
 }
 
