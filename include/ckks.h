@@ -406,13 +406,18 @@ int ckks_batch_destroy(ckks_batch *batch);
  * output buffer; NULL = the null stream), and the job's kernels start only
  * after that event, so work the caller queued there before the submit is
  * complete first.  Work queued on other streams is not waited for.
- * The budget bounds the device memory the server itself takes: the scratch
- * of the jobs on the device (ckks_workspace_bytes of the job's operation).
- * Inputs, keys and outputs are not counted: the caller allocated them before
- * the submit, so admitting a job does not change their footprint (keys are
- * typically shared by many jobs).  A job whose scratch alone exceeds the
- * budget is refused with CKKS_ENOMEM.  Latencies are host wall-clock from
- * submit to the worker observing completion.
+ * By default the budget bounds the device memory the server itself takes:
+ * the scratch of the jobs on the device (ckks_workspace_bytes of the job's
+ * operation).  Inputs, keys and outputs are then not counted: the caller
+ * allocated them before the submit, so admitting a job does not change their
+ * footprint (keys are typically shared by many jobs).  With
+ * ckks_server_set_accounting(server, 1) the budget covers each in-flight
+ * job's whole footprint instead: its scratch, its inputs and output, and
+ * every distinct key array (beta_max x 2 x (L_max + k) limbs) named by the
+ * jobs on the device, counted once however many jobs share it.  A job whose
+ * scratch (whole footprint) alone exceeds the budget is refused with
+ * CKKS_ENOMEM.  Latencies are host wall-clock from submit to the worker
+ * observing completion.
  */
 typedef struct ckks_server ckks_server;
 
@@ -431,6 +436,10 @@ int ckks_server_submit(ckks_server *server, int ctx_index, const ckks_job *job, 
 int ckks_server_poll(ckks_server *server, uint64_t ticket, int *done);
 /* Block until every submitted job has completed. */
 int ckks_server_drain(ckks_server *server);
+/* Admission accounting: 0 = job scratch only (default), 1 = whole footprint
+ * (scratch + inputs + output + distinct keys).  Before the first submit,
+ * else CKKS_EINVAL.  stats.peak_bytes reports the accounted peak. */
+int ckks_server_set_accounting(ckks_server *server, int whole_footprint);
 int ckks_server_stats(ckks_server *server, ckks_stats *stats);
 /* Submit / completion times (us since server creation; completion < 0 while
  * pending) of tickets [first, first + n). */

@@ -21,7 +21,7 @@ __all__ = [
     "JOB", "ckks_job", "ckks_batch_create", "ckks_batch_launch", "ckks_batch_device_bytes",
     "ckks_batch_destroy", "ckks_batch_plan", "ckks_batch_get_plan", "ckks_batch_set_plan",
     "ckks_batch_tune", "ckks_batch_tune_log", "ckks_stats", "ckks_server_create", "ckks_server_submit",
-    "ckks_server_poll", "ckks_server_drain", "ckks_server_stats", "ckks_server_times",
+    "ckks_server_poll", "ckks_server_drain", "ckks_server_set_accounting", "ckks_server_stats", "ckks_server_times",
     "ckks_server_destroy", "ckks_pmult_sum", "ckks_add", "ckks_schedule", "ckks_ctx_get_schedule",
     "ckks_ctx_set_schedule", "ckks_ctx_tune", "ckks_batch_get_schedule", "ckks_batch_set_schedule",
 ]
@@ -123,6 +123,7 @@ _SIGS = {
     "ckks_server_submit": [_vp, _i, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
     "ckks_server_poll": [_vp, ctypes.c_uint64, ctypes.POINTER(_i)],
     "ckks_server_drain": [_vp],
+    "ckks_server_set_accounting": [_vp, _i],
     "ckks_server_stats": [_vp, _vp],
     "ckks_server_times": [_vp, ctypes.c_uint64, _i, _vp, _vp],
     "ckks_server_destroy": [_vp],
@@ -401,6 +402,10 @@ def ckks_server_poll(server, ticket) -> bool:
 
 def ckks_server_drain(server):
     _check(lib().ckks_server_drain(server))
+
+
+def ckks_server_set_accounting(server, whole_footprint):
+    _check(lib().ckks_server_set_accounting(server, int(whole_footprint)))
 
 
 def ckks_server_stats(server) -> dict:

@@ -94,7 +94,9 @@ struct Req {
   uint64_t ticket;
   int ctx;
   ckks_job job;
-  size_t bytes;
+  size_t bytes;      // scratch (from the arena)
+  size_t io_bytes;   // inputs and output
+  size_t key_bytes;  // the key array (0 for rescale)
   hipEvent_t ready;  // recorded on the submitter's stream: the job's inputs are written
   void* src;         // that stream
 };
@@ -107,6 +109,8 @@ struct Flight {
   // the jobs' submit events and streams (until the waits are enqueued)
   std::vector<std::pair<void*, hipEvent_t>> ready;
   std::vector<std::pair<size_t, size_t>> allocs;
+  size_t io_bytes = 0;                // whole-footprint mode: inputs and outputs
+  std::vector<const void*> keys;      // whole-footprint mode: key references
   int ks_jobs;
 };
 
@@ -145,6 +149,11 @@ struct ckks_server {
   std::vector<hipEvent_t> event_pool;
   std::vector<hipEvent_t> all_events;
   int jobs_on_device = 0;
+  // whole-footprint accounting (ckks_server_set_accounting): the budget also
+  // covers the in-flight jobs' inputs and outputs and each distinct key once
+  int whole = 0;
+  size_t io_used = 0, key_used = 0, total_peak = 0;
+  std::map<const void*, std::pair<int, size_t>> key_refs;  // key -> (in-flight jobs, bytes)
   uint64_t next_ticket = 0;
   std::vector<double> t_submit, t_done;  // by ticket; t_done < 0 while pending
   std::vector<uint8_t> is_ks;
@@ -154,6 +163,22 @@ struct ckks_server {
   size_t job_bytes(const Ctx& c, const ckks_job& j) const {
     return align_up((j.op == CKKS_JOB_RESCALE ? rs_ws_words(c, j.L) : ks_ws_words(c, j.L)) * 4);
   }
+  // Inputs and output of a job (limbs of N words): ct [2][L] in (d [L] for a
+  // plain key-switch, a second ct for HMult), [2][L] out ([2][L-1] rescale).
+  static size_t io_bytes_of(const Ctx& c, const ckks_job& j) {
+    const size_t limb = (size_t)c.N * 4, L = (size_t)j.L;
+    switch (j.op) {
+      case CKKS_JOB_KEYSWITCH: return (L + 2 * L) * limb;
+      case CKKS_JOB_HMULT: return (4 * L + 2 * L) * limb;
+      case CKKS_JOB_RESCALE: return (2 * L + 2 * (L - 1)) * limb;
+      default: return (2 * L + 2 * L) * limb;
+    }
+  }
+  // The whole key array the job names: [beta_max][2][L_max + k] limbs.
+  static size_t key_bytes_of(const Ctx& c, const ckks_job& j) {
+    return j.op == CKKS_JOB_RESCALE ? 0 : (size_t)c.beta_max() * 2 * (c.L_max + c.k) * c.N * 4;
+  }
+  size_t total_used() const { return arena.used + io_used + key_used; }
 
   void retire_locked() {
     while (!inflight.empty()) {
@@ -171,6 +196,14 @@ struct ckks_server {
         completed_ks += is_ks[tk];
       }
       for (auto& a : f.allocs) arena.release(a.first, a.second);
+      io_used -= f.io_bytes;
+      for (const void* k : f.keys) {
+        auto it = key_refs.find(k);
+        if (it != key_refs.end() && --it->second.first == 0) {
+          key_used -= it->second.second;
+          key_refs.erase(it);
+        }
+      }
       jobs_on_device -= (int)f.tickets.size();
       ring_busy[f.ring] = false;
       inflight.pop_front();
@@ -196,8 +229,25 @@ struct ckks_server {
     int nks = 0, nrs = 0, Lks = 0, Lrs = 0;
     while (!pending.empty() && pending.front().ctx == ci && jobs_on_device + nks + nrs < max_slots) {
       Req& r = pending.front();
+      if (whole) {
+        const bool new_key = r.key_bytes && key_refs.find(r.job.key) == key_refs.end();
+        if (total_used() + r.bytes + r.io_bytes + (new_key ? r.key_bytes : 0) > budget) break;
+      }
       size_t off;
       if (!arena.alloc(r.bytes, &off)) break;
+      if (whole) {
+        io_used += r.io_bytes;
+        f.io_bytes += r.io_bytes;
+        if (r.key_bytes) {
+          auto& ref = key_refs[r.job.key];
+          if (ref.first++ == 0) {
+            ref.second = r.key_bytes;
+            key_used += r.key_bytes;
+          }
+          f.keys.push_back(r.job.key);
+        }
+        total_peak = std::max(total_peak, total_used());
+      }
       uint32_t* ws = (uint32_t*)((char*)d_arena + off);
       const ckks_job& j = r.job;
       if (j.op == CKKS_JOB_RESCALE) {
@@ -368,11 +418,13 @@ int ckks_server_submit(ckks_server* s, int ctx_index, const ckks_job* job, void*
   if (j.op != CKKS_JOB_RESCALE && (!j.key || (j.op == CKKS_JOB_HMULT && !j.in1)))
     return api_fail(CKKS_EINVAL, "null key or second input");
   const size_t bytes = s->job_bytes(c, j);
+  const size_t io = ckks_server::io_bytes_of(c, j), keyb = ckks_server::key_bytes_of(c, j);
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->error) return api_fail(s->error, s->error_msg);
-  if (bytes > s->budget) {
+  if (bytes > s->budget || (s->whole && bytes + io + keyb > s->budget)) {
     ++s->rejected;
-    return api_fail(CKKS_ENOMEM, "job scratch exceeds the server's HBM budget");
+    return api_fail(CKKS_ENOMEM, s->whole ? "job footprint exceeds the server's HBM budget"
+                                          : "job scratch exceeds the server's HBM budget");
   }
   // order the job after the work queued so far on the submitter's stream
   int prev = 0;
@@ -397,7 +449,7 @@ int ckks_server_submit(ckks_server* s, int ctx_index, const ckks_job* job, void*
   s->t_submit.push_back(now_us(s->t0));
   s->t_done.push_back(-1.0);
   s->is_ks.push_back(j.op != CKKS_JOB_RESCALE);
-  s->pending.push_back(Req{tk, ctx_index, j, bytes, ready, stream});
+  s->pending.push_back(Req{tk, ctx_index, j, bytes, io, keyb, ready, stream});
   s->cv_work.notify_one();
   *ticket = tk;
   return CKKS_OK;
@@ -441,7 +493,15 @@ int ckks_server_stats(ckks_server* s, ckks_stats* st) {
   st->max_us = lat.empty() ? 0.0 : *std::max_element(lat.begin(), lat.end());
   st->ks_per_s = (last > first && first >= 0) ? (double)s->completed_ks / ((last - first) * 1e-6) : 0.0;
   st->budget_bytes = s->budget;
-  st->peak_bytes = s->arena.peak;
+  st->peak_bytes = s->whole ? s->total_peak : s->arena.peak;
+  return CKKS_OK;
+}
+
+int ckks_server_set_accounting(ckks_server* s, int whole_footprint) {
+  if (!s) return api_fail(CKKS_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->next_ticket) return api_fail(CKKS_EINVAL, "accounting must be chosen before the first submit");
+  s->whole = whole_footprint != 0;
   return CKKS_OK;
 }
 

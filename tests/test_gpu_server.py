@@ -2,8 +2,9 @@
 submitted over time while earlier ones run; every result must equal the
 result of the same job run alone (tolerance 0: the arithmetic is exact), and
 a seeded sample equals the oracle.  Jobs wait for the work queued before
-them on the submitting stream.  Admission respects the HBM budget; oversize
-jobs are refused."""
+them on the submitting stream.  Admission respects the HBM budget (job
+scratch, or with whole-footprint accounting scratch + inputs + output +
+distinct keys); oversize jobs are refused."""
 import random
 import time
 
@@ -173,3 +174,50 @@ def test_budget_limits_admission_and_refuses_oversize(contexts):
             P.ckks_server_submit(srv, 0, dict(op=P.JOB["KEYSWITCH"], L=0, in0=key, key=key, out=key))
     finally:
         P.ckks_server_destroy(srv)
+
+
+def test_whole_footprint_budget_covers_inputs_outputs_and_keys(contexts):
+    """With whole-footprint accounting the budget bounds each in-flight job's
+    scratch, inputs and output plus every distinct key once: a budget of one
+    HMult's footprint runs four HMults one batch at a time (with scratch-only
+    accounting the same budget would hold all four), one of two footprints
+    sharing a key holds two, and a job larger than the budget is refused."""
+    spec, ctx = contexts[1]
+    L, N = 12, spec.N
+    limb = N * 4
+    scratch = P.ckks_workspace_bytes(ctx.handle, P.OP["HMULT"], L)
+    io = (4 * L + 2 * L) * limb
+    key_bytes = spec.beta(spec.L_max) * 2 * (spec.L_max + spec.k) * limb
+    one = scratch + io + key_bytes
+    assert 4 * scratch <= one + scratch // 2  # scratch-only: all four fit the first budget
+    rng = ci.Rng(71)
+    key = dev(rng.evk(spec))
+
+    def jobs(n):
+        return [dict(op=P.JOB["HMULT"], L=L, in0=dev(rng.polys(2, spec.q[:L], N)),
+                     in1=dev(rng.polys(2, spec.q[:L], N)), key=key, out=empty(2, L, N)) for _ in range(n)]
+
+    for budget, lone in ((one + scratch // 2, True), (one + scratch + io, False)):
+        batch = jobs(4)
+        srv = P.ckks_server_create([ctx.handle], budget, 8)
+        try:
+            P.ckks_server_set_accounting(srv, 1)
+            for j in batch:
+                P.ckks_server_submit(srv, 0, j)
+            with pytest.raises(P.CkksError):
+                P.ckks_server_set_accounting(srv, 0)  # only before the first submit
+            P.ckks_server_drain(srv)
+            st = P.ckks_server_stats(srv)
+            assert st["completed"] == 4 and one <= st["peak_bytes"] <= budget
+            if lone:
+                assert st["batches"] == 4
+            big = dict(op=P.JOB["HMULT"], L=spec.L_max, in0=batch[0]["in0"], in1=batch[0]["in1"], key=key,
+                       out=batch[0]["out"])
+            with pytest.raises(P.CkksError) as e:
+                P.ckks_server_submit(srv, 0, big)  # footprint at L_max exceeds the budget
+            assert e.value.code == -2
+        finally:
+            P.ckks_server_destroy(srv)
+        for i, j in enumerate(batch):
+            msg = first_mismatch(host(j["out"]), _alone(ctx, j))
+            assert not msg, f"budget {budget}: job {i}: {msg}"
