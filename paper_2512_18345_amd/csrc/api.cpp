@@ -152,27 +152,6 @@ uint32_t galois(const Ctx& c, int rot) {
 
 // ---- compositions ---------------------------------------------------------
 
-// ModUp of d [L][N] into M [beta][L + k][N]; y: [L][N] scratch.
-int modup_impl(const Ctx& c, const uint32_t* d, int L, uint32_t* M, uint32_t* y, hipStream_t st) {
-  const size_t N = c.N;
-  const int R = L + c.k;
-  const RowMap rm = c.rows(L);
-  CKKS_TRY(launch_intt(c, d, y, L, rm, 0, 0, c.d_modup_scale + (size_t)L * c.L_max, 0, st),
-           "ModUp INTT");
-  for (int j = 0; j < c.beta(L); ++j) {
-    const int lo = j * c.alpha, hi = std::min(lo + c.alpha, L);
-    uint32_t* Mj = M + (size_t)j * R * N;
-    CKKS_TRY(launch_bconv(c, rm, y + lo * N, hi - lo, Mj, R, lo, hi,
-                          c.d_modup_T + c.modup_T_off[(size_t)L * c.beta_max() + j], c.alpha, st),
-             "ModUp BConv");
-    CKKS_TRY(hipMemcpyAsync(Mj + lo * N, d + lo * N, (size_t)(hi - lo) * N * 4,
-                            hipMemcpyDeviceToDevice, st),
-             "ModUp digit copy");
-    CKKS_TRY(launch_ntt(c, Mj, Mj, R, rm, lo, hi, st), "ModUp NTT");
-  }
-  return CKKS_OK;
-}
-
 // ModDown of a [L + k][N] into out [L][N] (+ add if non-null); x: [k][N], z: [L][N] scratch.
 int moddown_impl(const Ctx& c, const uint32_t* a, int L, const uint32_t* add, uint32_t* out,
                  uint32_t* x, uint32_t* z, hipStream_t st) {
@@ -473,8 +452,11 @@ int ckks_modup(const ckks_ctx* ctx, const uint32_t* d, int L, uint32_t* out, voi
   const Ctx& c = ctx->c;
   if ((rc = check_ws(c, CKKS_OP_MODUP, L, ws, ws_bytes_given))) return rc;
   DeviceGuard g(c.device);
-  WS w{(char*)ws, ws_bytes_given};
-  return modup_impl(c, d, L, out, w.take(words(c, L)), (hipStream_t)stream);
+  JobArg<KsJob> mj{};
+  mj.table = nullptr;
+  mj.inl[0] = KsJob{KS_MODUP, L, 0, 0, d, nullptr, nullptr, out, (uint32_t*)ws};
+  CKKS_TRY(ks_modup_launch(c, c.sched, mj, 1, L, (hipStream_t)stream), "ModUp");
+  return CKKS_OK;
 }
 
 int ckks_inner_product(const ckks_ctx* ctx, const uint32_t* M, int L, const uint32_t* evk,
@@ -570,7 +552,11 @@ int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int*
   WS w{(char*)ws, ws_bytes_given};
   uint32_t* M = w.take(words(c, (size_t)c.beta(L) * (L + c.k)));
   uint32_t* y = w.take(words(c, L));
-  if ((rc = modup_impl(c, ct + (size_t)L * N, L, M, y, st))) return rc;
+  // the shared ModUp of c1 through the fused stage-1 kernels
+  JobArg<KsJob> mj{};
+  mj.table = nullptr;
+  mj.inl[0] = KsJob{KS_MODUP, L, 0, 0, ct + (size_t)L * N, nullptr, nullptr, M, y};
+  CKKS_TRY(ks_modup_launch(c, c.sched, mj, 1, L, st), "hoisted ModUp");
   uint32_t* job_ws[kInlineJobs];
   for (int i = 0; i < kInlineJobs; ++i) job_ws[i] = w.take(ks_hoist_ws_words(c, L));
   for (int i0 = 0; i0 < n; i0 += kInlineJobs) {

@@ -25,11 +25,12 @@ __global__ __launch_bounds__(kWG) void k_ntt_cols(DevTab T, RowMap rm, const uin
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, T.col_tw(pi), ColGeom<LOGN1>::N1);
+  const uint2 tww = tw_fetch(T.col_tw(pi), ColGeom<LOGN1>::N1);
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int col0 = blockIdx.x * ColGeom<LOGN1>::C;
   load_cols<LOGN1>(s, src + r * N, col0);
+  tw_put(stw, tww, ColGeom<LOGN1>::N1);
   __syncthreads();
   col_stages<LOGN1, false>(s, stw, q, q2);
   __syncthreads();
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uin
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   __shared__ uint2 stw[256];
-  stage_tw_perm(stw, T.blk_tw(pi));
+  const uint2 tww = tw_fetch(T.blk_tw(pi), 256);
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(kWG) void k_ntt_blks(DevTab T, RowMap rm, const uin
     lds_blk4_store(s, e, twist4(ld4(in + e),
                                 T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
   }
+  tw_put_perm(stw, tww);
   __syncthreads();
   blk_stages<false>(s, PermTw{stw}, q, q2);
   __syncthreads();
@@ -76,25 +78,29 @@ __global__ __launch_bounds__(kWG) void k_intt_blks(DevTab T, RowMap rm, const ui
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   __shared__ uint2 stw[256];
-  stage_tw_perm(stw, T.blk_itw(pi));
+  const uint2 tww = tw_fetch(T.blk_itw(pi), 256);
   const size_t N = (size_t)1 << T.logN;
   const uint32_t q = ldc(T.mod + pi).q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
   const uint32_t* in = src + r * N + blk0 * 256;
   uint32_t* out = dst + r * N + blk0 * 256;
+  uint4 x[4];
+  Twist4 tfi[4];  // the epilogue's twist factors, requested with the tile
+#pragma unroll
+  for (int k = 0; k < 4; ++k) x[k] = ld4(in + blk_elem(k));
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = blk_elem(k);
-    lds_blk4_store(s, e, ld4(in + e));
+    tfi[k] = twist4_load(T.blk_itwist(pi, blk0 + (e >> 8)), e & 255);
   }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) lds_blk4_store(s, blk_elem(k), x[k]);
+  tw_put_perm(stw, tww);
   __syncthreads();
   blk_stages<true>(s, PermTw{stw}, q, q2);
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int e = blk_elem(k);
-    st4(out + e, twist4(lds_blk4(s, e), T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q));
-  }
+  for (int k = 0; k < 4; ++k) st4(out + blk_elem(k), twist4(lds_blk4(s, blk_elem(k)), tfi[k], q));
 }
 
 // Inverse column pass + per-row scale (N^-1 times an optional base-conversion
@@ -110,13 +116,14 @@ __global__ __launch_bounds__(kWG) void k_intt_cols(DevTab T, RowMap rm, const ui
   if (r >= skip_lo && r < skip_hi) return;
   const int pi = rm.pidx(r);
   __shared__ uint2 stw[ColGeom<LOGN1>::N1];
-  stage_tw(stw, T.col_itw(pi), ColGeom<LOGN1>::N1);
+  const uint2 tww = tw_fetch(T.col_itw(pi), ColGeom<LOGN1>::N1);
   const size_t N = (size_t)1 << T.logN;
   const ModC mc = T.mod[pi];
   const uint32_t q = mc.q, q2 = 2 * q;
   const uint2 sc = scale ? scale[pi - scale_off] : make_uint2(mc.ninv, mc.ninv_s);
   const int col0 = blockIdx.x * C;
   load_cols<LOGN1>(s, src + r * N, col0);
+  tw_put(stw, tww, ColGeom<LOGN1>::N1);
   __syncthreads();
   col_stages<LOGN1, true>(s, stw, q, q2);
   __syncthreads();

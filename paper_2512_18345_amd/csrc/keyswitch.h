@@ -17,6 +17,8 @@ enum KsKind : int {
   KS_HMULT = 1,  // a = ct1, b = ct2 [2][L][N]; out = (d0 + KS_0(d2), d1 + KS_1(d2))
   KS_HROT = 2,   // a = ct [2][L][N]; out = (sigma(c0) + KS_0(sigma(c1)), KS_1(sigma(c1)))
   KS_HOIST = 3,  // a = ct, b = ModUp(c1) [beta][L + k][N]; out as HROT but from sigma(ModUp(c1))
+  KS_MODUP = 4,  // ModUp alone (the shared ModUp of hoisted rotations): a = d [L][N] (evaluation
+                 // domain), out = M [beta][L + k][N] (every row, the digit rows copied), ws = [L][N]
 };
 
 struct __align__(16) KsJob {
@@ -79,6 +81,10 @@ size_t rs_ws_words(const Ctx& c, int L);
 // is KS_HOIST.
 hipError_t ks_launch(const Ctx& c, const Ctx::Sched& sc, const JobArg<KsJob>& jobs, int njobs, int Lmax,
                      bool with_modup, bool with_hoist, hipStream_t st, const KsSplit& sp = KsSplit{});
+// Enqueue the ModUp of njobs KS_MODUP jobs (K1-K4 and the block pass of the
+// new rows: M ends fully in the evaluation domain, canonical).
+hipError_t ks_modup_launch(const Ctx& c, const Ctx::Sched& sc, const JobArg<KsJob>& jobs, int njobs, int Lmax,
+                           hipStream_t st);
 // Enqueue rescale (drop the top prime) for njobs jobs.
 hipError_t rs_launch(const Ctx& c, const JobArg<RsJob>& jobs, int njobs, int Lmax, hipStream_t st);
 

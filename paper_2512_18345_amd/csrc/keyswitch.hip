@@ -66,6 +66,12 @@ __device__ __forceinline__ KsView ks_view(const KsJob& J, const KsConst& K, size
   v.L = J.L;
   v.R = J.L + K.k;
   v.beta = (J.L + K.alpha - 1) / K.alpha;
+  if (J.kind == KS_MODUP) {  // ModUp alone: y in the scratch, z is the output M
+    v.y = J.ws;
+    v.z = J.out;
+    v.acc = v.x = v.w = v.de = nullptr;
+    return v;
+  }
   v.acc = J.ws;
   v.x = v.acc + (size_t)2 * v.R * N;
   v.w = v.x + (size_t)2 * K.k * N;
@@ -94,7 +100,7 @@ __device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const ModC& m
 template <int QPT = 4, int T = kWG>
 __device__ __forceinline__ void load_d16(const KsJob& J, int r, uint32_t base, size_t N, int logN,
                                          const ModC& m, uint4 d[QPT]) {
-  if (J.kind == KS_PLAIN) {
+  if (J.kind == KS_PLAIN || J.kind == KS_MODUP) {
 #pragma unroll
     for (int kk = 0; kk < QPT; ++kk) d[kk] = ld4(J.a + (size_t)r * N + base + blk_elem<T>(kk));
     return;
@@ -139,25 +145,36 @@ __global__ __launch_bounds__(BPW * 256 / EPT) void k1_intt_blks(KsConst K, JobAr
   const ModC m = ldc(K.T.mod + r);
   const uint32_t q = m.q, q2 = 2 * q;
   __shared__ uint2 stw[256];
-  if constexpr (EPT == 16)  // (T >= 256)
-    stage_tw_perm(stw, K.T.blk_itw(r));
-  else
-    stage_tw(stw, K.T.blk_itw(r), 256);
+  const uint2 tww = tw_fetch(K.T.blk_itw(r), 256);  // (T >= 256)
   constexpr int T = BPW * 256 / EPT;  // threads
   constexpr int QPT = EPT / 4;        // quads per thread
   const int blk0 = blockIdx.x * BPW;
   const uint32_t base = blk0 * 256;
   const KsView V = ks_view(J, K, N);
-  uint32_t* de = V.de + (size_t)r * N + base;
-  // all loads first: a store to de could alias the next quad's source
+  // the switched polynomial in the evaluation domain, kept for K5's digit
+  // rows (a ModUp-only job keeps it as the digit row of its output M)
+  uint32_t* de = J.kind == KS_MODUP ? V.z + ((size_t)(r / K.alpha) * V.R + r) * N + base
+                                    : V.de + (size_t)r * N + base;
+  // all loads first: a store to de could alias the next quad's source; the
+  // twist factors of the epilogue are requested with them
   uint4 d[QPT];
   load_d16<QPT, T>(J, r, base, N, logN, m, d);
+  Twist4 tfi[QPT];
+#pragma unroll
+  for (int kk = 0; kk < QPT; ++kk) {
+    const int e = blk_elem<T>(kk);
+    tfi[kk] = twist4_load(K.T.blk_itwist(r, blk0 + (e >> 8)), e & 255);
+  }
 #pragma unroll
   for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem<T>(kk);
     lds_blk4_store(s, e, d[kk]);
-    if (J.kind != KS_PLAIN) st4(de + e, d[kk]);
+    if (J.kind != KS_PLAIN) st4(de + e, d[kk]);  // HMULT, HROT, MODUP
   }
+  if constexpr (EPT == 16)
+    tw_put_perm(stw, tww);
+  else
+    tw_put(stw, tww, 256);
   __syncthreads();
   if constexpr (EPT == 16)
     blk_stages<true>(s, PermTw{stw}, q, q2);
@@ -168,10 +185,7 @@ __global__ __launch_bounds__(BPW * 256 / EPT) void k1_intt_blks(KsConst K, JobAr
   __syncthreads();
   uint32_t* y = V.y + (size_t)r * N + base;
 #pragma unroll
-  for (int kk = 0; kk < QPT; ++kk) {
-    const int e = blk_elem<T>(kk);
-    st4(y + e, twist4(lds_blk4(s, e), K.T.blk_itwist(r, blk0 + (e >> 8)), e & 255, q));
-  }
+  for (int kk = 0; kk < QPT; ++kk) st4(y + blk_elem<T>(kk), twist4(lds_blk4(s, blk_elem<T>(kk)), tfi[kk], q));
 }
 
 template <int LOGN1, int CW, int T>
@@ -184,11 +198,12 @@ __global__ __launch_bounds__(T) void k2_intt_cols(KsConst K, JobArg<KsJob> JA) {
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + r).q, q2 = 2 * q;
   __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
-  stage_tw(stw, K.T.col_itw(r), ColGeom<LOGN1, CW, T>::N1);
+  const uint2 tww = tw_fetch(K.T.col_itw(r), ColGeom<LOGN1, CW, T>::N1);
   const uint2 sc = ldc(K.modup_scale + (size_t)J.L * K.T.L_max + r);
   const int col0 = blockIdx.x * C;
   uint32_t* row = ks_view(J, K, N).y + (size_t)r * N;
   load_cols<LOGN1, CW, T>(s, row, col0);
+  tw_put(stw, tww, ColGeom<LOGN1, CW, T>::N1);
   __syncthreads();
   col_stages<LOGN1, true, CW, T>(s, stw, q, q2);
   __syncthreads();
@@ -256,15 +271,53 @@ __global__ __launch_bounds__(T) void k4_ntt_cols(KsConst K, JobArg<KsJob> JA) {
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
   __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
-  stage_tw(stw, K.T.col_tw(pi), ColGeom<LOGN1, CW, T>::N1);
+  const uint2 tww = tw_fetch(K.T.col_tw(pi), ColGeom<LOGN1, CW, T>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
   const int col0 = blockIdx.x * ColGeom<LOGN1, CW, T>::C;
   uint32_t* row = V.z + (size_t)gr * N;
   load_cols<LOGN1, CW, T>(s, row, col0);
+  tw_put(stw, tww, ColGeom<LOGN1, CW, T>::N1);
   __syncthreads();
   col_stages<LOGN1, false, CW, T>(s, stw, q, q2);
   __syncthreads();
   store_cols<LOGN1, CW, T>(s, row, col0);
+}
+
+// ModUp-only jobs: the block pass of the new rows of M (K4 left them after the
+// column pass), canonical output in place, so that M is wholly in the
+// evaluation domain for the hoisted rotations' gathers.
+template <int LOGN1>
+__global__ __launch_bounds__(kWG) void km_ntt_blks(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  if (J.kind != KS_MODUP) return;
+  const size_t N = (size_t)1 << K.T.logN;
+  const KsView V = ks_view(J, K, N);
+  const int gr = blockIdx.y;
+  const int j = gr / V.R, r = gr % V.R;
+  if (j >= V.beta) return;
+  const int lo = j * K.alpha, hi = min(lo + K.alpha, V.L);
+  if (r >= lo && r < hi) return;
+  __shared__ __align__(16) uint32_t s[kLds];
+  __shared__ uint2 stw[256];
+  const int pi = ks_pidx(r, V.L, K.T.L_max);
+  const uint2 tww = tw_fetch(K.T.blk_tw(pi), 256);
+  const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
+  const int blk0 = blockIdx.x * 16;
+  uint32_t* row = V.z + (size_t)gr * N + blk0 * 256;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    lds_blk4_store(s, e, twist4(ld4(row + e), K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
+  }
+  tw_put_perm(stw, tww);
+  __syncthreads();
+  blk_stages<false>(s, PermTw{stw}, q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    st4(row + e, canon4(lds_blk4(s, e), q, q2));
+  }
 }
 
 // ============================================================================
@@ -284,8 +337,10 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
   __shared__ __align__(16) uint32_t s[kLds];
   const int pi = ks_pidx(r, V.L, K.T.L_max);
   __shared__ uint2 stw[256], stwi[256];
-  stage_tw_perm(stw, K.T.blk_tw(pi));
-  if (r >= V.L) stage_tw_perm(stwi, K.T.blk_itw(pi));
+  // twiddles: requested now, stored to LDS after the first tile's loads
+  const uint2 tww = HOIST ? make_uint2(0, 0) : tw_fetch(K.T.blk_tw(pi), 256);
+  const uint2 twwi = r >= V.L ? tw_fetch(K.T.blk_itw(pi), 256) : make_uint2(0, 0);
+  bool tw_staged = false;
   const ModC m = ldc(K.T.mod + pi);
   const uint32_t q = m.q, q2 = 2 * q;
   const int blk0 = blockIdx.x * 16;
@@ -320,6 +375,10 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
         const int e = blk_elem(kk);
         lds_blk4_store(s, e, twist4(ld4(zrow + e),
                                     K.T.blk_twist(pi, blk0 + (e >> 8)), e & 255, q));
+      }
+      if (!tw_staged) {
+        tw_put_perm(stw, tww);
+        tw_staged = true;
       }
       __syncthreads();
       blk_stages<false>(s, PermTw{stw}, q, q2);
@@ -375,7 +434,15 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
     }
     return;
   }
-  // P rows: ModDown starts with an INTT; its block pass runs here on the tile.
+  // P rows: ModDown starts with an INTT; its block pass runs here on the tile
+  // (inverse twist factors requested before the transforms).
+  Twist4 tfi[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    tfi[kk] = twist4_load(K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255);
+  }
+  tw_put_perm(stwi, twwi);
   for (int c = 0; c < 2; ++c) {
     uint32_t* dst = c ? acc1 : acc0;
     __syncthreads();
@@ -388,10 +455,7 @@ __global__ __launch_bounds__(kWG) void k5_ntt_blks_ip(KsConst K, JobArg<KsJob> J
     blk_stages<true>(s, PermTw{stwi}, q, q2);
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int e = blk_elem(kk);
-      st4(dst + e, twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q));
-    }
+    for (int kk = 0; kk < 4; ++kk) st4(dst + blk_elem(kk), twist4(lds_blk4(s, blk_elem(kk)), tfi[kk], q));
   }
 }
 
@@ -545,6 +609,7 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
   // inverse twiddles in the same pads (the forward ones were last read before
   // the barrier that ended the transforms); the inverse twist factors are
   // requested first, so their latency overlaps the transforms
+  const uint2 twi_word = K.T.blk_itw(pi)[threadIdx.x];
   Twist4 tfi[4];
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
@@ -552,7 +617,131 @@ __global__ __launch_bounds__(kWG) void k5s_ntt_blks_ip(KsConst K, JobArg<KsJob> 
     tfi[kk] = twist4_load(K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255);
   }
   __syncthreads();
-  stage_tw_pads_perm(s, K.T.blk_itw(pi));
+  stage_tw_pads_perm_word(s, twi_word);
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    lds_blk4_store(s, blk_elem(kk), res0[kk]);
+    lds_blk4_store(s + kLds, blk_elem(kk), res1[kk]);
+  }
+  __syncthreads();
+  blk_stages<true>(s, PadTwP{s}, q, q2);
+  blk_stages<true>(s + kLds, PadTwP{s}, q, q2);
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    st4(acc0 + e, twist4(lds_blk4(s, e), tfi[kk], q));
+    st4(acc1 + e, twist4(lds_blk4(s + kLds, e), tfi[kk], q));
+  }
+}
+
+// K5 for hoisted rotations of at most NB digits.  sigma_g maps each aligned
+// 4096-word tile of an evaluation-domain row onto one aligned source tile (g
+// is odd, so only the low 12 bits of the bit-reversed index are permuted), so
+// every digit's source tile of M is loaded whole and contiguously into its
+// own LDS slot and the permutation is a read from LDS.  The key words of the
+// first KPF quads are requested with the tiles; the inner product and the
+// P-row INTT block pass follow as in k5s, on canonical words (M is fully
+// transformed).
+template <int LOGN1, int NB>
+__global__ __launch_bounds__(kWG) void k5h_gather_ip(KsConst K, JobArg<KsJob> JA, int part) {
+  static_assert(NB >= 2 && NB <= 4, "slots for two to four digits");
+  const KsJob J = JA.get(blockIdx.z);
+  const int logN = K.T.logN;
+  const size_t N = (size_t)1 << logN;
+  const KsView V = ks_view(J, K, N);
+  const int r = blockIdx.y + (part == KS_PART_P ? V.L : 0);
+  if (r >= V.R || (part == KS_PART_Q && r >= V.L) || J.kind != KS_HOIST) return;
+  constexpr int WORDS = NB * kTile > 2 * kLds ? NB * kTile : 2 * kLds;
+  __shared__ __align__(16) uint32_t s[WORDS];
+  const int pi = ks_pidx(r, V.L, K.T.L_max);
+  const ModC m = ldc(K.T.mod + pi);
+  const uint32_t q = m.q;
+  const int blk0 = blockIdx.x * 16;
+  const uint32_t base = blk0 * 256;
+  const size_t KR = (size_t)K.T.L_max + K.k;  // key rows
+  const uint32_t src0 = auto_src(base, J.gal, logN) & ~(uint32_t)(kTile - 1);
+  // every digit's source tile (digits past beta re-read the last one, unused)
+  uint4 raw[NB][4];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int jj = min(j, V.beta - 1);
+    const uint32_t* Mrow = J.b + ((size_t)jj * V.R + r) * N + src0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) raw[j][kk] = ld4(Mrow + 4 * (threadIdx.x + kk * kWG));
+  }
+  constexpr int KPF = NB <= 2 ? 4 : 2;
+  uint4 kpre0[4][NB], kpre1[4][NB];
+  auto key_quad = [&](int kk) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const uint32_t* k0 = J.key + ((size_t)min(j, V.beta - 1) * 2 * KR + pi) * N + base + blk_elem(kk);
+      kpre0[kk][j] = ld4nt(k0);
+      kpre1[kk][j] = ld4nt(k0 + KR * N);
+    }
+  };
+#pragma unroll
+  for (int kk = 0; kk < KPF; ++kk) key_quad(kk);
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      *reinterpret_cast<uint4*>(s + j * kTile + 4 * (threadIdx.x + kk * kWG)) = raw[j][kk];
+  __syncthreads();
+
+  // inner product of sigma(M) quad by quad (canonical words: products below
+  // 2^60, at most four summed, one reduction per output)
+  uint4 res0[4], res1[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    const uint32_t n = base + e;
+    const uint32_t p0 = auto_src(n, J.gal, logN) & (kTile - 1), p1 = auto_src(n + 1, J.gal, logN) & (kTile - 1),
+                   p2 = auto_src(n + 2, J.gal, logN) & (kTile - 1), p3 = auto_src(n + 3, J.gal, logN) & (kTile - 1);
+    if (kk >= KPF) key_quad(kk);
+    uint64_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const uint32_t msk = j < V.beta ? ~0u : 0u;
+      const uint32_t* sl = s + j * kTile;
+      const uint4 v = make_uint4(sl[p0] & msk, sl[p1] & msk, sl[p2] & msk, sl[p3] & msk);
+      const uint4 e0 = kpre0[kk][j], e1 = kpre1[kk][j];
+      a0[0] += (uint64_t)v.x * e0.x;
+      a0[1] += (uint64_t)v.y * e0.y;
+      a0[2] += (uint64_t)v.z * e0.z;
+      a0[3] += (uint64_t)v.w * e0.w;
+      a1[0] += (uint64_t)v.x * e1.x;
+      a1[1] += (uint64_t)v.y * e1.y;
+      a1[2] += (uint64_t)v.z * e1.z;
+      a1[3] += (uint64_t)v.w * e1.w;
+    }
+    res0[kk] = make_uint4(reduce64(a0[0], q, m.mu_hi, m.mu_lo), reduce64(a0[1], q, m.mu_hi, m.mu_lo),
+                          reduce64(a0[2], q, m.mu_hi, m.mu_lo), reduce64(a0[3], q, m.mu_hi, m.mu_lo));
+    res1[kk] = make_uint4(reduce64(a1[0], q, m.mu_hi, m.mu_lo), reduce64(a1[1], q, m.mu_hi, m.mu_lo),
+                          reduce64(a1[2], q, m.mu_hi, m.mu_lo), reduce64(a1[3], q, m.mu_hi, m.mu_lo));
+  }
+  uint32_t* acc0 = V.acc + (size_t)r * N + base;
+  uint32_t* acc1 = V.acc + ((size_t)V.R + r) * N + base;
+  if (r < V.L) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int e = blk_elem(kk);
+      st4(acc0 + e, res0[kk]);
+      st4(acc1 + e, res1[kk]);
+    }
+    return;
+  }
+  // P rows: the INTT block pass of ModDown on both components, as in k5s
+  const uint32_t q2 = 2 * q;
+  const uint2 twi_word = K.T.blk_itw(pi)[threadIdx.x];
+  Twist4 tfi[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int e = blk_elem(kk);
+    tfi[kk] = twist4_load(K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255);
+  }
+  __syncthreads();  // the gathers have read the slots
+  stage_tw_pads_perm_word(s, twi_word);
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     lds_blk4_store(s, blk_elem(kk), res0[kk]);
@@ -746,11 +935,12 @@ __global__ __launch_bounds__(T) void k6_intt_cols_p(KsConst K, JobArg<KsJob> JA)
   constexpr int C = ColGeom<LOGN1, CW, T>::C;
   const int pi = K.T.L_max + mm;
   __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
-  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW, T>::N1);
+  const uint2 tww = tw_fetch(K.T.col_itw(pi), ColGeom<LOGN1, CW, T>::N1);
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
   const uint2 sc = ldc(K.moddown_scale + mm);
   const int col0 = blockIdx.x * C;
   load_cols<LOGN1, CW, T>(s, V.acc + ((size_t)c * V.R + V.L + mm) * N, col0);
+  tw_put(stw, tww, ColGeom<LOGN1, CW, T>::N1);
   __syncthreads();
   col_stages<LOGN1, true, CW, T>(s, stw, q, q2);
   __syncthreads();
@@ -808,12 +998,13 @@ __global__ __launch_bounds__(T) void k8_ntt_cols_w(KsConst K, JobArg<KsJob> JA) 
   if (gr >= 2 * V.L) return;
   const int i = gr % V.L;
   __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
-  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, CW, T>::N1);
+  const uint2 tww = tw_fetch(K.T.col_tw(i), ColGeom<LOGN1, CW, T>::N1);
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
   const int col0 = blockIdx.x * ColGeom<LOGN1, CW, T>::C;
   uint32_t* row = V.w + (size_t)gr * N;
   load_cols<LOGN1, CW, T>(s, row, col0);
+  tw_put(stw, tww, ColGeom<LOGN1, CW, T>::N1);
   __syncthreads();
   col_stages<LOGN1, false, CW, T>(s, stw, q, q2);
   __syncthreads();
@@ -832,10 +1023,7 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
   if (gr >= 2 * V.L) return;
   const int c = gr / V.L, i = gr % V.L;
   __shared__ uint2 stw[256];
-  if constexpr (BPW == 16)
-    stage_tw_perm(stw, K.T.blk_tw(i));
-  else
-    stage_tw(stw, K.T.blk_tw(i), 256);
+  const uint2 tww = tw_fetch(K.T.blk_tw(i), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const ModC m = ldc(K.T.mod + i);
   const uint32_t q = m.q, q2 = 2 * q;
@@ -849,6 +1037,10 @@ __global__ __launch_bounds__(kWG) void k9_ntt_blks_combine(KsConst K, JobArg<KsJ
     lds_blk4_store(s, e, twist4(ld4(wrow + e),
                                 K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
+  if constexpr (BPW == 16)
+    tw_put_perm(stw, tww);
+  else
+    tw_put(stw, tww, 256);
   __syncthreads();
   if constexpr (BPW == 16)
     blk_stages<false>(s, PermTw{stw}, q, q2);
@@ -917,10 +1109,7 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, L = J.L, pi = L - 1;
   __shared__ uint2 stw[256];
-  if constexpr (BPW == 16)
-    stage_tw_perm(stw, K.T.blk_itw(pi));
-  else
-    stage_tw(stw, K.T.blk_itw(pi), 256);
+  const uint2 tww = tw_fetch(K.T.blk_itw(pi), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + pi).q, q2 = 2 * q;
@@ -928,11 +1117,21 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
   const int blk0 = blockIdx.x * BPW;
   const uint32_t* in = J.a + ((size_t)c * L + pi) * N + blk0 * 256;
   uint32_t* t = J.ws + (size_t)c * N + blk0 * 256;
+  uint4 x[QPT];
+  Twist4 tfi[QPT];  // the epilogue's twist factors, requested with the tile
+#pragma unroll
+  for (int kk = 0; kk < QPT; ++kk) x[kk] = ld4(in + blk_elem(kk));
 #pragma unroll
   for (int kk = 0; kk < QPT; ++kk) {
     const int e = blk_elem(kk);
-    lds_blk4_store(s, e, ld4(in + e));
+    tfi[kk] = twist4_load(K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255);
   }
+#pragma unroll
+  for (int kk = 0; kk < QPT; ++kk) lds_blk4_store(s, blk_elem(kk), x[kk]);
+  if constexpr (BPW == 16)
+    tw_put_perm(stw, tww);
+  else
+    tw_put(stw, tww, 256);
   __syncthreads();
   if constexpr (BPW == 16)
     blk_stages<true>(s, PermTw{stw}, q, q2);
@@ -940,10 +1139,7 @@ __global__ __launch_bounds__(kWG) void r1_intt_blks(KsConst K, JobArg<RsJob> JA)
     blk_stages_r4<true, const uint2*, kWG>(s, stw, q, q2);
   __syncthreads();
 #pragma unroll
-  for (int kk = 0; kk < QPT; ++kk) {
-    const int e = blk_elem(kk);
-    st4(t + e, twist4(lds_blk4(s, e), K.T.blk_itwist(pi, blk0 + (e >> 8)), e & 255, q));
-  }
+  for (int kk = 0; kk < QPT; ++kk) st4(t + blk_elem(kk), twist4(lds_blk4(s, blk_elem(kk)), tfi[kk], q));
 }
 
 template <int LOGN1, int CW, int T>
@@ -951,7 +1147,7 @@ __global__ __launch_bounds__(T) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
   const RsJob J = JA.get(blockIdx.z);
   const int c = blockIdx.y, pi = J.L - 1;
   __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
-  stage_tw(stw, K.T.col_itw(pi), ColGeom<LOGN1, CW, T>::N1);
+  const uint2 tww = tw_fetch(K.T.col_itw(pi), ColGeom<LOGN1, CW, T>::N1);
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
   constexpr int C = ColGeom<LOGN1, CW, T>::C;
   const size_t N = (size_t)1 << K.T.logN;
@@ -960,6 +1156,7 @@ __global__ __launch_bounds__(T) void r2_intt_cols(KsConst K, JobArg<RsJob> JA) {
   const int col0 = blockIdx.x * C;
   uint32_t* row = J.ws + (size_t)c * N;
   load_cols<LOGN1, CW, T>(s, row, col0);
+  tw_put(stw, tww, ColGeom<LOGN1, CW, T>::N1);
   __syncthreads();
   col_stages<LOGN1, true, CW, T>(s, stw, q, q2);
   __syncthreads();
@@ -985,7 +1182,7 @@ __global__ __launch_bounds__(T) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) {
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
   __shared__ uint2 stw[ColGeom<LOGN1, CW, T>::N1];
-  stage_tw(stw, K.T.col_tw(i), ColGeom<LOGN1, CW, T>::N1);
+  const uint2 tww = tw_fetch(K.T.col_tw(i), ColGeom<LOGN1, CW, T>::N1);
   __shared__ __align__(16) uint32_t s[ColGeom<LOGN1, CW, T>::LDS];
   constexpr int C = ColGeom<LOGN1, CW, T>::C;
   const size_t N = (size_t)1 << K.T.logN;
@@ -1004,6 +1201,7 @@ __global__ __launch_bounds__(T) void r3_ntt_cols(KsConst K, JobArg<RsJob> JA) {
     v.w = reduce32(v.w, q, m.mu32);
     *reinterpret_cast<uint4*>(s + lidx_col(pos, cc, C)) = v;
   }
+  tw_put(stw, tww, ColGeom<LOGN1, CW, T>::N1);
   __syncthreads();
   col_stages<LOGN1, false, CW, T>(s, stw, q, q2);
   __syncthreads();
@@ -1018,7 +1216,7 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
   if (gr >= 2 * L1) return;
   const int c = gr / L1, i = gr % L1;
   __shared__ uint2 stw[256];
-  stage_tw_perm(stw, K.T.blk_tw(i));
+  const uint2 tww = tw_fetch(K.T.blk_tw(i), 256);
   __shared__ __align__(16) uint32_t s[kLds];
   const size_t N = (size_t)1 << K.T.logN;
   const uint32_t q = ldc(K.T.mod + i).q, q2 = 2 * q;
@@ -1031,6 +1229,7 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
     lds_blk4_store(s, e, twist4(ld4(u + e),
                                 K.T.blk_twist(i, blk0 + (e >> 8)), e & 255, q));
   }
+  tw_put_perm(stw, tww);
   __syncthreads();
   blk_stages<false>(s, PermTw{stw}, q, q2);
   __syncthreads();
@@ -1187,6 +1386,37 @@ void col_launch(const Ctx& c, int stage, int rows, int njobs, bool sparse, hipSt
   klaunch_b(c, stage, KF<L1, 0, kColThreads<L1>>::fn, dim3(TL, rows, njobs), kColThreads<L1>, st, K, jobs);
 }
 
+// Stage 1 (ModUp): K1-K4.
+template <int L1>
+hipError_t modup_stage_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, const JobArg<KsJob>& jobs,
+                         int njobs, int Lmax, hipStream_t st) {
+  const int Rmax = Lmax + c.k;
+  const int tiles = c.N / kTile;
+  const int cols = c.N / (4 * kWG);  // BConv: four coefficients per thread
+  const int bmax = c.beta(Lmax);
+  const int up_rows = sc.up_rows == 2 || sc.up_rows == 4 || sc.up_rows == 6 ? sc.up_rows : 12;
+  const int up_groups = (Rmax + up_rows - 1) / up_rows;
+  if (4 * tiles * Lmax * njobs <= 256)  // quarter tiles still one work-group per CU
+    klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 4>, dim3(4 * tiles, Lmax, njobs), st, K, jobs);
+  else
+    klaunch_b(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16, 8>, dim3(tiles, Lmax, njobs), 512, st, K, jobs);
+  col_launch<K2c, L1>(c, CKKS_STAGE_INTT_COLS, Lmax, njobs, true, st, K, jobs);
+  const hipError_t e =
+      small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups, up_rows);
+  if (e != hipSuccess) return e;
+  col_launch<K4c, L1>(c, CKKS_STAGE_NTT_COLS_UP, bmax * Rmax, njobs, false, st, K, jobs);
+  return hipSuccess;
+}
+
+template <int L1>
+hipError_t ks_modup_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, const JobArg<KsJob>& jobs,
+                             int njobs, int Lmax, hipStream_t st) {
+  const hipError_t e = modup_stage_t<L1>(c, sc, K, jobs, njobs, Lmax, st);
+  if (e != hipSuccess) return e;
+  klaunch(c, -1, km_ntt_blks<L1>, dim3(c.N / kTile, c.beta(Lmax) * (Lmax + c.k), njobs), st, K, jobs);
+  return hipGetLastError();
+}
+
 template <int L1>
 hipError_t ks_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, const JobArg<KsJob>& jobs,
                        int njobs, int Lmax, bool with_modup, bool with_hoist, hipStream_t st,
@@ -1194,23 +1424,10 @@ hipError_t ks_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, con
   const int Rmax = Lmax + c.k;
   const int tiles = c.N / kTile;
   const int cols = c.N / (4 * kWG);  // BConv: four coefficients per thread
-  const int bmax = c.beta(Lmax);
-  auto rows_of = [](int r) { return r == 2 || r == 4 || r == 6 ? r : 12; };
-  const int up_rows = rows_of(sc.up_rows), down_rows = rows_of(sc.down_rows);
-  const int up_groups = (Rmax + up_rows - 1) / up_rows;
+  const int down_rows = sc.down_rows == 2 || sc.down_rows == 4 || sc.down_rows == 6 ? sc.down_rows : 12;
   const int down_groups = (Lmax + down_rows - 1) / down_rows;
   hipError_t e;
-  if (with_modup) {
-    if (4 * tiles * Lmax * njobs <= 256)  // quarter tiles still one work-group per CU
-      klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 4>, dim3(4 * tiles, Lmax, njobs), st, K, jobs);
-    else
-      klaunch_b(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16, 8>, dim3(tiles, Lmax, njobs), 512, st, K, jobs);
-    col_launch<K2c, L1>(c, CKKS_STAGE_INTT_COLS, Lmax, njobs, true, st, K, jobs);
-    e = small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups,
-                              up_rows);
-    if (e != hipSuccess) return e;
-    col_launch<K4c, L1>(c, CKKS_STAGE_NTT_COLS_UP, bmax * Rmax, njobs, false, st, K, jobs);
-  }
+  if (with_modup && (e = modup_stage_t<L1>(c, sc, K, jobs, njobs, Lmax, st)) != hipSuccess) return e;
   // Stage 2.  With a side stream, complementary pipelining (Sec. IV-B): the
   // inner product of the P rows runs on st and ModDown's P-row chain (K6..K8,
   // latency-bound) follows it there, while the Q-row inner product (key
@@ -1269,7 +1486,13 @@ hipError_t ks_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, con
     }
   };
   auto k5h = [&](int stage, int part, hipStream_t s5, int rows) {
-    klaunch(c, stage, k5_ntt_blks_ip<L1, true>, dim3(tiles, rows, njobs), s5, K, jobs, part);
+    const dim3 gh(tiles, rows, njobs);
+    switch (std::max(c.beta(Lmax), 2)) {  // slots for the launch's own largest digit count
+      case 2: klaunch(c, stage, k5h_gather_ip<L1, 2>, gh, s5, K, jobs, part); break;
+      case 3: klaunch(c, stage, k5h_gather_ip<L1, 3>, gh, s5, K, jobs, part); break;
+      case 4: klaunch(c, stage, k5h_gather_ip<L1, 4>, gh, s5, K, jobs, part); break;
+      default: klaunch(c, stage, k5_ntt_blks_ip<L1, true>, gh, s5, K, jobs, part); break;
+    }
   };
   const bool split = sp.side != nullptr;
   auto fork = [&]() -> hipError_t {
@@ -1336,6 +1559,20 @@ hipError_t ks_launch(const Ctx& c, const Ctx::Sched& sc, const JobArg<KsJob>& jo
     case 6: return ks_launch_t<6>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
     case 7: return ks_launch_t<7>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
     case 8: return ks_launch_t<8>(c, sc, K, jobs, njobs, Lmax, with_modup, with_hoist, st, sp);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t ks_modup_launch(const Ctx& c, const Ctx::Sched& sc, const JobArg<KsJob>& jobs, int njobs, int Lmax,
+                           hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  const KsConst K = make_const(c);
+  switch (c.logN - kBlockLog) {
+    case 4: return ks_modup_launch_t<4>(c, sc, K, jobs, njobs, Lmax, st);
+    case 5: return ks_modup_launch_t<5>(c, sc, K, jobs, njobs, Lmax, st);
+    case 6: return ks_modup_launch_t<6>(c, sc, K, jobs, njobs, Lmax, st);
+    case 7: return ks_modup_launch_t<7>(c, sc, K, jobs, njobs, Lmax, st);
+    case 8: return ks_modup_launch_t<8>(c, sc, K, jobs, njobs, Lmax, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -390,6 +390,23 @@ __device__ __forceinline__ void stage_tw_perm(uint2* stw, const uint2* __restric
   if (t < 256) stw[t ? tw_perm_of(t) : 0] = tw[t];
 }
 
+// The same staging in two halves, so that no kernel waits for its twiddles
+// before it has requested its tile: tw_fetch issues the global load of the
+// thread's entry (threads past n load nothing), tw_put / tw_put_perm store it
+// to LDS once the tile's loads are in flight.
+__device__ __forceinline__ uint2 tw_fetch(const uint2* __restrict__ tw, int n) {
+  uint2 w = make_uint2(0, 0);
+  if ((int)threadIdx.x < n) w = tw[threadIdx.x];
+  return w;
+}
+__device__ __forceinline__ void tw_put(uint2* stw, uint2 w, int n) {
+  if ((int)threadIdx.x < n) stw[threadIdx.x] = w;
+}
+__device__ __forceinline__ void tw_put_perm(uint2* stw, uint2 w) {
+  const int t = threadIdx.x;
+  if (t < 256) stw[t ? tw_perm_of(t) : 0] = w;
+}
+
 template <int LOGN1, int CW = 0, int T = kWG>
 __device__ __forceinline__ void load_cols(uint32_t* s, const uint32_t* __restrict__ row, int col0) {
   using G = ColGeom<LOGN1, CW, T>;
