@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--no-trace", action="store_true", help="skip the short bootstrapping-shaped trace run")
     ap.add_argument("--no-serve", action="store_true", help="skip the short serving run")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
-    ap.add_argument("--schedule", type=str, default="", metavar="UP,DOWN,SMALL",
+    ap.add_argument("--schedule", type=str, default="", metavar="UP,DOWN,SMALL[,SHAPE]",
                     help="run under this kernel schedule instead of the autotuned one")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -256,7 +256,15 @@ int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, 
  *   small_grid       inner-product launches of at most this many
  *                    work-groups use one thread group per digit tile
  *                    (0: never)
- * Default {12, 6, 128}.  The schedule is read when work is enqueued (and when
+ *   ntt_shape        NTT tile / radix choices (Sec. III-C1 NTT kernels),
+ *                    a bit mask: 1 = forward column passes with 8 elements
+ *                    per thread in radix-8 phases (else 16, radix-16);
+ *                    2 = inverse column passes with 16 elements per thread
+ *                    in radix-16 phases (else 8, radix-8); 4 = the ModUp
+ *                    INTT block pass with 16 elements per thread on 256
+ *                    threads (else 8 on 512).  Small grids keep their own
+ *                    shapes.  0..7.
+ * Default {12, 6, 128, 0}.  The schedule is read when work is enqueued (and when
  * a graph batch is captured); changing it must not overlap calls on the
  * context.  Every schedule gives bitwise the same results.
  */
@@ -264,16 +272,18 @@ typedef struct ckks_schedule {
     int bconv_up_rows;
     int bconv_down_rows;
     int small_grid;
-    int reserved;
+    int ntt_shape;
 } ckks_schedule;
 
 int ckks_ctx_get_schedule(const ckks_ctx *ctx, ckks_schedule *sched);
-/* Errors: CKKS_EINVAL for rows outside {2, 4, 6, 12} or small_grid outside [0, 65535]. */
+/* Errors: CKKS_EINVAL for rows outside {2, 4, 6, 12}, small_grid outside [0, 65535]
+ * or ntt_shape outside [0, 7]. */
 int ckks_ctx_set_schedule(ckks_ctx *ctx, const ckks_schedule *sched);
 /*
  * Schedule autotuner: times an HMult at level L on synthetic inputs (zeros;
  * the arithmetic is data-independent) under every candidate schedule
- * (rows in {2, 4, 6, 12} for both BConvs, small_grid in {0, 128, 1024}), one
+ * (rows in {2, 4, 6, 12} for both BConvs, small_grid in {0, 128, 1024},
+ * ntt_shape 0..7: 384 candidates), one
  * warm-up and `reps` calls each between two events on `stream`, and keeps
  * the fastest.  Allocates its own device buffers (inputs, key, workspace)
  * for the duration of the call and synchronises `stream`; not for use while
@@ -365,11 +375,13 @@ int ckks_batch_set_schedule(ckks_batch *batch, const ckks_schedule *sched);
  * Autotuner: times candidate plans (jobs_per_launch in {all, 32, 16, 8, 4, 2}
  * below the job count, streams 1..4 up to the number of groups (1 for a
  * graph batch), split 0/1/2) under the batch's schedule, then, under the
- * best plan, up to four other kernel schedules ({12, 6, 128}, {6, 4, 128},
- * {4, 6, 128}, {12, 12, 128}): each candidate as one warm-up launch then
- * `reps` launches between two events on `stream`; keeps the fastest plan and
- * schedule (graph batches are re-captured and timed as graph launches).
- * Runs the batch up to 76 x (reps + 1) times and synchronises `stream`:
+ * best plan, up to four other BConv schedules ({12, 6, 128}, {6, 4, 128},
+ * {4, 6, 128}, {12, 12, 128}, with the batch's ntt_shape), then the other
+ * seven NTT shapes under the best of those: each candidate as one warm-up
+ * launch then `reps` launches between two events on `stream`; keeps the
+ * fastest plan and schedule (graph batches are re-captured and timed as graph
+ * launches).  Runs the batch up to 83 x (reps + 1) times and synchronises
+ * `stream`:
  * outputs are written, inputs only read.  best / best_us (either may be
  * NULL) receive the chosen plan and its time per launch in microseconds;
  * ckks_batch_get_schedule gives the chosen schedule.  On error the previous

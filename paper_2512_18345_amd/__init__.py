@@ -53,11 +53,11 @@ class ckks_job(ctypes.Structure):
 class ckks_schedule(ctypes.Structure):
     """Mirror of struct ckks_schedule (include/ckks.h)."""
     _fields_ = [("bconv_up_rows", ctypes.c_int), ("bconv_down_rows", ctypes.c_int),
-                ("small_grid", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("small_grid", ctypes.c_int), ("ntt_shape", ctypes.c_int)]
 
     def as_dict(self):
         return dict(bconv_up_rows=self.bconv_up_rows, bconv_down_rows=self.bconv_down_rows,
-                    small_grid=self.small_grid)
+                    small_grid=self.small_grid, ntt_shape=self.ntt_shape)
 
 
 class ckks_batch_plan(ctypes.Structure):
@@ -313,8 +313,8 @@ def ckks_ctx_get_schedule(ctx) -> dict:
     return s.as_dict()
 
 
-def ckks_ctx_set_schedule(ctx, bconv_up_rows=12, bconv_down_rows=6, small_grid=128):
-    s = ckks_schedule(int(bconv_up_rows), int(bconv_down_rows), int(small_grid), 0)
+def ckks_ctx_set_schedule(ctx, bconv_up_rows=12, bconv_down_rows=6, small_grid=128, ntt_shape=0):
+    s = ckks_schedule(int(bconv_up_rows), int(bconv_down_rows), int(small_grid), int(ntt_shape))
     _check(lib().ckks_ctx_set_schedule(ctx, ctypes.cast(ctypes.byref(s), _vp)))
 
 
@@ -333,8 +333,8 @@ def ckks_batch_get_schedule(batch) -> dict:
     return s.as_dict()
 
 
-def ckks_batch_set_schedule(batch, bconv_up_rows=12, bconv_down_rows=6, small_grid=128):
-    s = ckks_schedule(int(bconv_up_rows), int(bconv_down_rows), int(small_grid), 0)
+def ckks_batch_set_schedule(batch, bconv_up_rows=12, bconv_down_rows=6, small_grid=128, ntt_shape=0):
+    s = ckks_schedule(int(bconv_up_rows), int(bconv_down_rows), int(small_grid), int(ntt_shape))
     _check(lib().ckks_batch_set_schedule(batch, ctypes.cast(ctypes.byref(s), _vp)))
 
 

@@ -589,7 +589,7 @@ int ckks_rescale(const ckks_ctx* ctx, const uint32_t* ct, int L, uint32_t* out, 
 int ckks_ctx_get_schedule(const ckks_ctx* ctx, ckks_schedule* sched) {
   if (!ctx || !sched) return fail(CKKS_EINVAL, "null argument");
   const Ctx::Sched& s = ctx->c.sched;
-  *sched = ckks_schedule{s.up_rows, s.down_rows, s.small_grid, 0};
+  *sched = ckks_schedule{s.up_rows, s.down_rows, s.small_grid, s.ntt_shape};
   return CKKS_OK;
 }
 
@@ -597,15 +597,15 @@ namespace {
 bool sched_ok(const ckks_schedule& s) {
   auto rows_ok = [](int r) { return r == 2 || r == 4 || r == 6 || r == 12; };
   return rows_ok(s.bconv_up_rows) && rows_ok(s.bconv_down_rows) && s.small_grid >= 0 &&
-         s.small_grid <= 65535;
+         s.small_grid <= 65535 && s.ntt_shape >= 0 && s.ntt_shape <= kShapeAll;
 }
 }  // namespace
 
 int ckks_ctx_set_schedule(ckks_ctx* ctx, const ckks_schedule* sched) {
   if (!ctx || !sched) return fail(CKKS_EINVAL, "null argument");
   if (!sched_ok(*sched))
-    return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12} and 0 <= small_grid <= 65535");
-  ctx->c.sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid};
+    return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12}, 0 <= small_grid <= 65535, 0 <= ntt_shape <= 7");
+  ctx->c.sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid, sched->ntt_shape};
   return CKKS_OK;
 }
 
@@ -644,11 +644,12 @@ int ckks_ctx_tune(ckks_ctx* ctx, int L, int reps, void* stream, ckks_schedule* b
   float top_us = -1.f;
   const uint32_t* ct1 = (const uint32_t*)d_ct;
   const uint32_t* ct2 = (const uint32_t*)((char*)d_ct + ct_b);
+  for (int shape = 0; shape <= kShapeAll; ++shape)
   for (int up : {12, 6, 4, 2}) {
     for (int down : {6, 12, 4, 2}) {
       for (int small : {128, 0, 1024}) {
         if (e != hipSuccess) break;
-        c.sched = Ctx::Sched{up, down, small};
+        c.sched = Ctx::Sched{up, down, small, shape};
         auto once = [&]() {
           return run_one(c, KS_HMULT, L, 0, ct1, ct2, (const uint32_t*)d_key, (uint32_t*)d_out, d_ws, st);
         };
@@ -679,7 +680,7 @@ int ckks_ctx_tune(ckks_ctx* ctx, int L, int reps, void* stream, ckks_schedule* b
   cleanup();
   c.sched = e == hipSuccess ? top : start;
   if (e != hipSuccess) return hip_fail(e, "timing candidate schedules");
-  if (best) *best = ckks_schedule{top.up_rows, top.down_rows, top.small_grid, 0};
+  if (best) *best = ckks_schedule{top.up_rows, top.down_rows, top.small_grid, top.ntt_shape};
   if (best_us) *best_us = top_us;
   return CKKS_OK;
 }
@@ -819,7 +820,7 @@ int ckks_batch_set_plan(ckks_batch* b, const ckks_batch_plan* plan) {
 
 int ckks_batch_get_schedule(const ckks_batch* b, ckks_schedule* sched) {
   if (!b || !sched) return fail(CKKS_EINVAL, "null argument");
-  *sched = ckks_schedule{b->sched.up_rows, b->sched.down_rows, b->sched.small_grid, 0};
+  *sched = ckks_schedule{b->sched.up_rows, b->sched.down_rows, b->sched.small_grid, b->sched.ntt_shape};
   return CKKS_OK;
 }
 
@@ -829,7 +830,7 @@ int ckks_batch_set_schedule(ckks_batch* b, const ckks_schedule* sched) {
     return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12} and 0 <= small_grid <= 65535");
   DeviceGuard g(b->c->device);
   const Ctx::Sched old = b->sched;
-  b->sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid};
+  b->sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid, sched->ntt_shape};
   if (b->use_graph) {
     const hipError_t e = batch_capture(b);
     if (e != hipSuccess) {
@@ -899,7 +900,8 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
   if (e == hipSuccess) {
     b->plan = top;
     e = batch_events(b, top);
-    const Ctx::Sched cands[] = {{12, 6, 128}, {6, 4, 128}, {4, 6, 128}, {12, 12, 128}};
+    const int sh = start_sched.ntt_shape;
+    const Ctx::Sched cands[] = {{12, 6, 128, sh}, {6, 4, 128, sh}, {4, 6, 128, sh}, {12, 12, 128, sh}};
     for (const Ctx::Sched& cs : cands) {
       if (e != hipSuccess) break;
       if (cs.up_rows == start_sched.up_rows && cs.down_rows == start_sched.down_rows &&
@@ -911,6 +913,19 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
       if (us < top_us) {
         top_us = us;
         top_sched = cs;
+      }
+    }
+    // 3) NTT tile / radix shapes under the best plan and BConv schedule
+    const Ctx::Sched base = top_sched;
+    for (int shape = 0; shape <= kShapeAll && e == hipSuccess; ++shape) {
+      if (shape == base.ntt_shape) continue;
+      b->sched = base;
+      b->sched.ntt_shape = shape;
+      float us = 0.f;
+      if ((e = time_it(&us)) != hipSuccess) break;
+      if (us < top_us) {
+        top_us = us;
+        top_sched = b->sched;
       }
     }
   }

@@ -110,8 +110,10 @@ struct Ctx {
   // ckks_ctx_tune): BConv output rows per work-group for ModUp and ModDown
   // (2, 4, 6 or 12), and the largest inner-product grid that uses one thread
   // group per digit (0: never).  Results do not depend on it.
+  // Kernel schedule: launch shapes only, results are bitwise the same under
+  // every schedule.  ntt_shape bits (kShape*): NTT tile and radix choices.
   struct Sched {
-    int up_rows = 12, down_rows = 6, small_grid = 128;
+    int up_rows = 12, down_rows = 6, small_grid = 128, ntt_shape = 0;
   };
   Sched sched;
   // The start / stop events for the next launch of a traced stage (both null

@@ -44,6 +44,13 @@ struct __align__(16) RsJob {
 
 constexpr int kInlineJobs = 16;
 
+// NTT shape bits of Ctx::Sched::ntt_shape (whole-line column tiles and the
+// ModUp INTT block pass; small grids keep their own shapes):
+constexpr int kShapeFwdRadix8 = 1;   // forward column passes: 8 elements / thread, radix-8 phases (else 16, radix-16)
+constexpr int kShapeInvRadix16 = 2;  // inverse column passes: 16 elements / thread, radix-16 phases (else 8, radix-8)
+constexpr int kShapeK1Radix16 = 4;   // ModUp INTT block pass: 16 elements / thread on 256 threads (else 8 on 512)
+constexpr int kShapeAll = 7;
+
 // Rows of the key inner product a K5 launch covers.
 enum KsPart : int { KS_PART_ALL = 0, KS_PART_P = 1, KS_PART_Q = 2 };
 

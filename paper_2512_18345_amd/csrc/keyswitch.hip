@@ -1357,11 +1357,12 @@ struct R3c { static constexpr auto fn = r3_ntt_cols<L1, CW, T>; };
 // columns (N <= 2^13).  Otherwise a `sparse` pass (one whose launches have
 // about one work-group per CU or fewer: the INTT passes K2, K6 and the
 // rescale's) takes the narrowest tiles in radix-4 phases under kNarrowBelow
-// work-groups and whole-line tiles with eight elements per thread in radix-8
-// phases above; the others take whole-line tiles of 16 elements per thread.
+// work-groups; above that, whole-line tiles with eight elements per thread in
+// radix-8 phases (radix8) or 16 per thread in radix-16 phases, as the
+// schedule's shape bits choose (col_radix8).
 template <template <int, int, int> class KF, int L1, class JA>
 void col_launch(const Ctx& c, int stage, int rows, int njobs, bool sparse, hipStream_t st,
-                const KsConst& K, const JA& jobs) {
+                const KsConst& K, const JA& jobs, bool radix8) {
   constexpr int TL = ColGeom<L1>::TILES;
   if constexpr (ColGeom<L1>::C / 4 >= 32) {
     if (4 * TL * rows * njobs <= 256) {
@@ -1378,12 +1379,17 @@ void col_launch(const Ctx& c, int stage, int rows, int njobs, bool sparse, hipSt
     klaunch_b(c, stage, KF<L1, CW, T>::fn, dim3(ColGeom<L1, CW>::TILES, rows, njobs), T, st, K, jobs);
     return;
   }
-  if (sparse) {  // 8 elements per thread: four waves per SIMD
+  if (radix8) {  // 8 elements per thread: four waves per SIMD
     constexpr int T = ColGeom<L1>::ELEMS / 8;
     klaunch_b(c, stage, KF<L1, 0, T>::fn, dim3(TL, rows, njobs), T, st, K, jobs);
     return;
   }
   klaunch_b(c, stage, KF<L1, 0, kColThreads<L1>>::fn, dim3(TL, rows, njobs), kColThreads<L1>, st, K, jobs);
+}
+// The whole-line radix of a column pass under schedule shape bits: sparse
+// (inverse) passes default to radix-8, the others to radix-16.
+inline bool col_radix8(bool sparse, int shape) {
+  return sparse ? !(shape & kShapeInvRadix16) : (shape & kShapeFwdRadix8) != 0;
 }
 
 // Stage 1 (ModUp): K1-K4.
@@ -1398,13 +1404,16 @@ hipError_t modup_stage_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, c
   const int up_groups = (Rmax + up_rows - 1) / up_rows;
   if (4 * tiles * Lmax * njobs <= 256)  // quarter tiles still one work-group per CU
     klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 4>, dim3(4 * tiles, Lmax, njobs), st, K, jobs);
+  else if (sc.ntt_shape & kShapeK1Radix16)
+    klaunch(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16, 16>, dim3(tiles, Lmax, njobs), st, K, jobs);
   else
     klaunch_b(c, CKKS_STAGE_INTT_BLOCKS, k1_intt_blks<L1, 16, 8>, dim3(tiles, Lmax, njobs), 512, st, K, jobs);
-  col_launch<K2c, L1>(c, CKKS_STAGE_INTT_COLS, Lmax, njobs, true, st, K, jobs);
+  col_launch<K2c, L1>(c, CKKS_STAGE_INTT_COLS, Lmax, njobs, true, st, K, jobs, col_radix8(true, sc.ntt_shape));
   const hipError_t e =
       small_dispatch<K3, 1>(c.alpha, c, dim3(cols, bmax * up_groups, njobs), st, K, jobs, up_groups, up_rows);
   if (e != hipSuccess) return e;
-  col_launch<K4c, L1>(c, CKKS_STAGE_NTT_COLS_UP, bmax * Rmax, njobs, false, st, K, jobs);
+  col_launch<K4c, L1>(c, CKKS_STAGE_NTT_COLS_UP, bmax * Rmax, njobs, false, st, K, jobs,
+                      col_radix8(false, sc.ntt_shape));
   return hipSuccess;
 }
 
@@ -1519,11 +1528,12 @@ hipError_t ks_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, con
     if (with_hoist) k5h(CKKS_STAGE_NTT_IP, KS_PART_ALL, st, Rmax);
   }
   if (split && (e = hipEventRecord(sp.join, sp.side)) != hipSuccess) return e;
-  col_launch<K6c, L1>(c, CKKS_STAGE_INTT_COLS_P, 2 * c.k, njobs, true, st, K, jobs);
+  col_launch<K6c, L1>(c, CKKS_STAGE_INTT_COLS_P, 2 * c.k, njobs, true, st, K, jobs, col_radix8(true, sc.ntt_shape));
   e = small_dispatch<K7, 1>(c.k, c, dim3(cols, 2 * down_groups, njobs), st, K, jobs, down_groups,
                             down_rows);
   if (e != hipSuccess) return e;
-  col_launch<K8c, L1>(c, CKKS_STAGE_NTT_COLS_DOWN, 2 * Lmax, njobs, false, st, K, jobs);
+  col_launch<K8c, L1>(c, CKKS_STAGE_NTT_COLS_DOWN, 2 * Lmax, njobs, false, st, K, jobs,
+                      col_radix8(false, sc.ntt_shape));
   if (split && (e = hipStreamWaitEvent(st, sp.join, 0)) != hipSuccess) return e;
   if (4 * tiles * 2 * Lmax * njobs <= 256)
     klaunch(c, CKKS_STAGE_NTT_COMBINE, k9_ntt_blks_combine<L1, 4>, dim3(4 * tiles, 2 * Lmax, njobs), st, K,
@@ -1541,8 +1551,8 @@ hipError_t rs_launch_t(const Ctx& c, const KsConst& K, const JobArg<RsJob>& jobs
     r1_intt_blks<L1, 4><<<dim3(4 * tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
   else
     r1_intt_blks<L1, 16><<<dim3(tiles, 2, njobs), kWG, 0, st>>>(K, jobs);
-  col_launch<R2c, L1>(c, -1, 2, njobs, true, st, K, jobs);
-  col_launch<R3c, L1>(c, -1, 2 * (Lmax - 1), njobs, false, st, K, jobs);
+  col_launch<R2c, L1>(c, -1, 2, njobs, true, st, K, jobs, col_radix8(true, c.sched.ntt_shape));
+  col_launch<R3c, L1>(c, -1, 2 * (Lmax - 1), njobs, false, st, K, jobs, col_radix8(false, c.sched.ntt_shape));
   klaunch(c, CKKS_STAGE_RESCALE_NTT, r4_ntt_blks_combine<L1>, dim3(tiles, 2 * (Lmax - 1), njobs), st, K,
           jobs);
   return hipGetLastError();

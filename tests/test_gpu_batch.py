@@ -175,10 +175,11 @@ def test_batch_schedules_give_the_single_call_results(use_graph):
     b = P.ckks_batch_create(ctx.handle, jobs, use_graph=use_graph)
     try:
         assert P.ckks_batch_get_schedule(b) == before
-        for sch in [(2, 12, 0), (12, 2, 65535), (6, 4, 128)]:
+        for sch in [(2, 12, 0, 3), (12, 2, 65535, 4), (6, 4, 128, 7)]:
             print(f"schedule {sch} graph={use_graph}", flush=True)
             P.ckks_batch_set_schedule(b, *sch)
-            assert P.ckks_batch_get_schedule(b) == dict(zip(("bconv_up_rows", "bconv_down_rows", "small_grid"), sch))
+            assert P.ckks_batch_get_schedule(b) == dict(
+                zip(("bconv_up_rows", "bconv_down_rows", "small_grid", "ntt_shape"), sch))
             for j in jobs:
                 j["out"].fill_(-1)
             P.ckks_batch_launch(b)

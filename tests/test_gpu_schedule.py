@@ -1,6 +1,7 @@
 """Kernel schedules (BConv rows per work-group, the per-digit inner-product
-variant for small grids) change only the launch shapes: every schedule, and
-the one the autotuner picks, must give the oracle's results bit for bit."""
+variant for small grids, the NTT tile / radix shapes) change only the launch
+shapes: every schedule, and the one the autotuner picks, must give the
+oracle's results bit for bit."""
 import pytest
 import torch
 
@@ -12,7 +13,9 @@ from gpu_helpers import dev, empty, first_mismatch, host
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
-SCHEDULES = [(12, 6, 128), (4, 4, 0), (6, 12, 512), (2, 2, 0), (4, 6, 65535), (2, 12, 1024)]
+SCHEDULES = [(12, 6, 128, 0), (4, 4, 0, 1), (6, 12, 512, 2), (2, 2, 0, 3), (4, 6, 65535, 4), (2, 12, 1024, 5),
+             (12, 4, 128, 6), (6, 2, 0, 7)]
+FIELDS = ("bconv_up_rows", "bconv_down_rows", "small_grid", "ntt_shape")
 
 
 @pytest.mark.parametrize("name,L", [("n16_l36", 36), ("n16_l36", 13), ("n12_l4", 4), ("toy_n12", 5)])
@@ -31,7 +34,7 @@ def test_every_schedule_matches_the_oracle(name, L):
     try:
         for sch in SCHEDULES:
             P.ckks_ctx_set_schedule(h, *sch)
-            assert P.ckks_ctx_get_schedule(h) == dict(zip(("bconv_up_rows", "bconv_down_rows", "small_grid"), sch))
+            assert P.ckks_ctx_get_schedule(h) == dict(zip(FIELDS, sch))
             out = empty(2, L, N)
             P.ckks_hmult(h, d1, d2, L, dk, out, ctx.workspace("HMULT", L))
             msg = first_mismatch(host(out), want_m)
@@ -51,8 +54,10 @@ def test_every_schedule_matches_the_oracle(name, L):
 
 def test_bad_schedules_are_rejected():
     ctx = P.Context.from_spec(ci.get("n12_l4"))
-    for sch in [(5, 6, 128), (12, 8, 128), (1, 6, 128), (12, 6, -1), (12, 6, 70000)]:
+    for sch in [(5, 6, 128), (12, 8, 128), (1, 6, 128), (12, 6, -1), (12, 6, 70000), (12, 6, 128, 8),
+                (12, 6, 128, -1)]:
         with pytest.raises(P.CkksError) as e:
             P.ckks_ctx_set_schedule(ctx.handle, *sch)
         assert e.value.code == -1
-    assert P.ckks_ctx_get_schedule(ctx.handle) == dict(bconv_up_rows=12, bconv_down_rows=6, small_grid=128)
+    assert P.ckks_ctx_get_schedule(ctx.handle) == dict(bconv_up_rows=12, bconv_down_rows=6, small_grid=128,
+                                                       ntt_shape=0)
