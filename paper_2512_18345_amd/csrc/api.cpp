@@ -190,6 +190,10 @@ struct ckks_batch {
   std::vector<int> L_ks;  // levels of the key-switching jobs in table order (non-increasing)
   KsJob* d_ks = nullptr;
   RsJob* d_rs = nullptr;
+  // host copies of the tables: launch groups of at most kInlineJobs jobs
+  // carry their jobs in the kernel arguments (no table read at kernel start)
+  std::vector<KsJob> h_ks;
+  std::vector<RsJob> h_rs;
   void* d_ws = nullptr;
   size_t bytes = 0;
   bool use_graph = false;
@@ -229,18 +233,29 @@ hipError_t batch_enqueue(ckks_batch* b, hipStream_t st) {
   for (int s0 = 0; s0 < b->n_ks; s0 += B, ++group) {
     const int br = group % S;
     JobArg<KsJob> ka{};
-    ka.table = b->d_ks + s0;
+    const int cnt = std::min(B, b->n_ks - s0);
+    if (cnt <= kInlineJobs) {
+      ka.table = nullptr;
+      for (int t = 0; t < cnt; ++t) ka.inl[t] = b->h_ks[s0 + t];
+    } else {
+      ka.table = b->d_ks + s0;
+    }
     if (b->plan.split && b->gev.size() < 2 * (size_t)group + 2) return hipErrorInvalidValue;
     const KsSplit sp = b->plan.split
                            ? KsSplit{b->side[br], b->gev[2 * group], b->gev[2 * group + 1], b->plan.split == 2}
                            : KsSplit{};
-    if ((e = ks_launch(c, b->sched, ka, std::min(B, b->n_ks - s0), b->L_ks[s0], true, false, on(br), sp)) !=
+    if ((e = ks_launch(c, b->sched, ka, cnt, b->L_ks[s0], true, false, on(br), sp)) !=
         hipSuccess)
       return e;
   }
   if (b->n_rs) {
     JobArg<RsJob> ra{};
-    ra.table = b->d_rs;
+    if (b->n_rs <= kInlineJobs) {
+      ra.table = nullptr;
+      for (int t = 0; t < b->n_rs; ++t) ra.inl[t] = b->h_rs[t];
+    } else {
+      ra.table = b->d_rs;
+    }
     if ((e = rs_launch(c, ra, b->n_rs, b->Lmax_rs, on(S - 1))) != hipSuccess) return e;
   }
   if (S > 1) {
@@ -751,6 +766,8 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
     b->L_ks.push_back(ks[i].L);
   }
   for (size_t i = 0; i < rs.size(); ++i) rs[i].ws = (uint32_t*)((char*)b->d_ws + rs_off[i]);
+  b->h_ks = sorted;
+  b->h_rs = rs;
   if ((!ks.empty() && hipMemcpy(b->d_ks, sorted.data(), sizeof(KsJob) * ks.size(), hipMemcpyHostToDevice) != hipSuccess) ||
       (!rs.empty() && hipMemcpy(b->d_rs, rs.data(), sizeof(RsJob) * rs.size(), hipMemcpyHostToDevice) != hipSuccess)) {
     batch_free(b);

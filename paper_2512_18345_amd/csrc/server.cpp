@@ -278,17 +278,24 @@ struct ckks_server {
     }
     for (auto& rv : f.ready) event_pool.push_back(rv.second);
     f.ready.clear();
-    if (e == hipSuccess && nks) e = hipMemcpyAsync(d_ks[ring], h_ks[ring], sizeof(KsJob) * nks, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && nrs)
+    // up to kInlineJobs jobs travel in the kernel arguments; larger groups
+    // through the ring slot's device table
+    if (e == hipSuccess && nks > kInlineJobs)
+      e = hipMemcpyAsync(d_ks[ring], h_ks[ring], sizeof(KsJob) * nks, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && nrs > kInlineJobs)
       e = hipMemcpyAsync(d_rs[ring], h_rs[ring], sizeof(RsJob) * nrs, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nks) {
       JobArg<KsJob> ka{};
-      ka.table = d_ks[ring];
+      ka.table = nks > kInlineJobs ? d_ks[ring] : nullptr;
+      if (!ka.table)
+        for (int t = 0; t < nks; ++t) ka.inl[t] = h_ks[ring][t];
       e = ks_launch(c, c.sched, ka, nks, Lks, true, false, st);
     }
     if (e == hipSuccess && nrs) {
       JobArg<RsJob> ra{};
-      ra.table = d_rs[ring];
+      ra.table = nrs > kInlineJobs ? d_rs[ring] : nullptr;
+      if (!ra.table)
+        for (int t = 0; t < nrs; ++t) ra.inl[t] = h_rs[ring][t];
       e = rs_launch(c, ra, nrs, Lrs, st);
     }
     f.ev = events[ring];
