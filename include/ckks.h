@@ -262,9 +262,13 @@ int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, 
  *                    2 = inverse column passes with 16 elements per thread
  *                    in radix-16 phases (else 8, radix-8); 4 = the ModUp
  *                    INTT block pass with 16 elements per thread on 256
- *                    threads (else 8 on 512).  Small grids keep their own
- *                    shapes.  0..7.
- * Default {12, 6, 128, 0}.  The schedule is read when work is enqueued (and when
+ *                    threads (else 8 on 512); 8 = at N = 2^12, the whole
+ *                    key-switch as two kernels that hold whole limbs in
+ *                    LDS (ModUp + inner product per row and digit group,
+ *                    ModDown + epilogue per output row) instead of the
+ *                    nine-kernel pipeline.  Small grids keep their own
+ *                    shapes.  0..15.
+ * Default {12, 6, 128, 0}; {12, 6, 128, 8} for N = 2^12.  The schedule is read when work is enqueued (and when
  * a graph batch is captured); changing it must not overlap calls on the
  * context.  Every schedule gives bitwise the same results.
  */
@@ -277,13 +281,13 @@ typedef struct ckks_schedule {
 
 int ckks_ctx_get_schedule(const ckks_ctx *ctx, ckks_schedule *sched);
 /* Errors: CKKS_EINVAL for rows outside {2, 4, 6, 12}, small_grid outside [0, 65535]
- * or ntt_shape outside [0, 7]. */
+ * or ntt_shape outside [0, 15]. */
 int ckks_ctx_set_schedule(ckks_ctx *ctx, const ckks_schedule *sched);
 /*
  * Schedule autotuner: times an HMult at level L on synthetic inputs (zeros;
  * the arithmetic is data-independent) under every candidate schedule
  * (rows in {2, 4, 6, 12} for both BConvs, small_grid in {0, 128, 1024},
- * ntt_shape 0..7: 384 candidates), one
+ * ntt_shape 0..7, and 8..15 at N = 2^12: 384 or 768 candidates), one
  * warm-up and `reps` calls each between two events on `stream`, and keeps
  * the fastest.  Allocates its own device buffers (inputs, key, workspace)
  * for the duration of the call and synchronises `stream`; not for use while

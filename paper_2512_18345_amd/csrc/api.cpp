@@ -376,6 +376,8 @@ int ckks_ctx_create(ckks_ctx** out, int logN, const uint32_t* h_q, int L_max, co
     delete ctx;
     return fail(code, err);
   }
+  // small rings run the key-switch on whole limbs by default
+  if (c.logN == kSrLog) c.sched.ntt_shape = kShapeWholeLimb;
   *out = ctx;
   return CKKS_OK;
 }
@@ -619,7 +621,7 @@ bool sched_ok(const ckks_schedule& s) {
 int ckks_ctx_set_schedule(ckks_ctx* ctx, const ckks_schedule* sched) {
   if (!ctx || !sched) return fail(CKKS_EINVAL, "null argument");
   if (!sched_ok(*sched))
-    return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12}, 0 <= small_grid <= 65535, 0 <= ntt_shape <= 7");
+    return fail(CKKS_EINVAL, "schedule needs rows in {2, 4, 6, 12}, 0 <= small_grid <= 65535, 0 <= ntt_shape <= 15");
   ctx->c.sched = Ctx::Sched{sched->bconv_up_rows, sched->bconv_down_rows, sched->small_grid, sched->ntt_shape};
   return CKKS_OK;
 }
@@ -661,6 +663,7 @@ int ckks_ctx_tune(ckks_ctx* ctx, int L, int reps, void* stream, ckks_schedule* b
   const uint32_t* ct2 = (const uint32_t*)((char*)d_ct + ct_b);
   for (int shape = 0; shape <= kShapeAll; ++shape)
   for (int up : {12, 6, 4, 2}) {
+    if ((shape & kShapeWholeLimb) && c.logN != kSrLog) break;  // the bit means nothing there
     for (int down : {6, 12, 4, 2}) {
       for (int small : {128, 0, 1024}) {
         if (e != hipSuccess) break;
@@ -935,7 +938,7 @@ int ckks_batch_tune(ckks_batch* b, int reps, void* stream, ckks_batch_plan* best
     // 3) NTT tile / radix shapes under the best plan and BConv schedule
     const Ctx::Sched base = top_sched;
     for (int shape = 0; shape <= kShapeAll && e == hipSuccess; ++shape) {
-      if (shape == base.ntt_shape) continue;
+      if (shape == base.ntt_shape || ((shape & kShapeWholeLimb) && b->c->logN != kSrLog)) continue;
       b->sched = base;
       b->sched.ntt_shape = shape;
       float us = 0.f;

@@ -36,7 +36,10 @@ struct ModC {
 //  * twist of block b: twist / itwist [nprimes][N1][32], entries j < 16 are
 //    rho_b^(+-j) and 16 + h are rho_b^(+-16 h), rho_b = psi^(2 brv_logN1(b) + 1);
 //    the block pass multiplies element j of block b by rho_b^j before the
-//    forward network (by rho_b^-j after the inverse one).
+//    forward network (by rho_b^-j after the inverse one);
+//  * whole-limb transforms of small rings (N = 2^kSrLog only, else null):
+//    ftw / fitw [nprimes][N], index m + i < N -> psi^(+-brv_logN(m + i)).
+constexpr int kSrLog = 12;
 struct DevTab {
   const ModC* mod;   // [nprimes]
   const uint2* tw;
@@ -45,6 +48,8 @@ struct DevTab {
   const uint2* ictw;
   const uint2* twist;
   const uint2* itwist;
+  const uint2* ftw;
+  const uint2* fitw;
   int logN;
   int L_max;
   __host__ __device__ int logN1() const { return logN - 8; }
@@ -58,6 +63,8 @@ struct DevTab {
   __device__ const uint2* blk_itwist(int pi, int b) const {
     return itwist + ((((size_t)pi << logN1()) + b) << 5);
   }
+  __device__ const uint2* full_tw(int pi) const { return ftw + ((size_t)pi << logN); }
+  __device__ const uint2* full_itw(int pi) const { return fitw + ((size_t)pi << logN); }
 };
 
 // Rows of a launch: row r of the data is prime index pidx(r).
@@ -83,6 +90,8 @@ struct Ctx {
   uint2* d_ictw = nullptr;
   uint2* d_twist = nullptr;   // [nprimes][N1][32]
   uint2* d_itwist = nullptr;
+  uint2* d_ftw = nullptr;     // [nprimes][N], N = 2^kSrLog only
+  uint2* d_fitw = nullptr;
   // ModUp at level L (1-based): per Q row i < L, (N^-1 * (D_j/q_i)^-1, Shoup) where j = i / alpha.
   uint2* d_modup_scale = nullptr;     // [L_max + 1][L_max]
   // ModUp BConv tables at level L, digit j: T[r][i] = (D_j / q_{j alpha + i}) mod prime(r),
@@ -129,7 +138,7 @@ struct Ctx {
   }
 
   DevTab tab() const {
-    return DevTab{d_mod, d_tw, d_itw, d_ctw, d_ictw, d_twist, d_itwist, logN, L_max};
+    return DevTab{d_mod, d_tw, d_itw, d_ctw, d_ictw, d_twist, d_itwist, d_ftw, d_fitw, logN, L_max};
   }
   RowMap rows(int L) const { return RowMap{L, L_max}; }
   int beta(int L) const { return (L + alpha - 1) / alpha; }

@@ -49,7 +49,8 @@ constexpr int kInlineJobs = 16;
 constexpr int kShapeFwdRadix8 = 1;   // forward column passes: 8 elements / thread, radix-8 phases (else 16, radix-16)
 constexpr int kShapeInvRadix16 = 2;  // inverse column passes: 16 elements / thread, radix-16 phases (else 8, radix-8)
 constexpr int kShapeK1Radix16 = 4;   // ModUp INTT block pass: 16 elements / thread on 256 threads (else 8 on 512)
-constexpr int kShapeAll = 7;
+constexpr int kShapeWholeLimb = 8;   // N = 2^kSrLog: two kernels with whole limbs in LDS instead of nine
+constexpr int kShapeAll = 15;
 
 // Rows of the key inner product a K5 launch covers.
 enum KsPart : int { KS_PART_ALL = 0, KS_PART_P = 1, KS_PART_Q = 2 };

@@ -1249,6 +1249,367 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
   }
 }
 
+
+// ============================================================================
+// Small rings (N = 2^kSrLog = 4096): a whole limb fits one work-group's LDS,
+// so the two-pass NTT split -- and with it the nine-kernel pipeline -- is not
+// needed.  A key-switch runs as two kernels of 1024-thread work-groups:
+//   S1  per (ModUp row t, group of digits): each non-digit limb of a digit
+//       transformed back whole in LDS, scaled, converted to row t (BConv),
+//       the sum transformed forward, times the key rows; the products summed
+//       over the group's digits -> one partial accumulator per group;
+//   S2  per (Q row i, component): the partials summed; ModDown -- the P rows'
+//       INTT whole in LDS, their conversion to q_i, its NTT -- combined with
+//       the accumulator, plus the job's epilogue term.
+// The arithmetic is that of the nine kernels (exact: the same residues).
+// Scratch of a job: the partials [groups][2][L + k][N] (at most 4 groups).
+// ============================================================================
+constexpr int kSrN = 1 << kSrLog;
+constexpr int kSrT = kSrN / 4;  // threads: one radix-4 unit / one quad each
+
+__device__ __forceinline__ int sr_per(int beta) { return (beta + 3) >> 2; }  // digits per group
+__device__ __forceinline__ int sr_groups(int beta) { return (beta + sr_per(beta) - 1) / sr_per(beta); }
+
+// Forward negacyclic NTT of the limb in s (natural coefficients in,
+// bit-reversed evaluations out) as six radix-4 phases; twiddle of group
+// (m, g) at tw[m + g].  Unit u of the phase on stages (ls, ls + 1) covers
+// a = 4 g t2 + i, a + t2, a + 2 t2, a + 3 t2 (t2 = N / (4 m), g = u / t2,
+// i = u % t2).  Words in [0, 4q) throughout (Harvey butterflies).
+__device__ __forceinline__ void sr_ntt(uint32_t* s, const uint2* tw, uint32_t q) {
+  const uint32_t q2 = 2 * q;
+  const int u = threadIdx.x;
+#pragma unroll
+  for (int ls = 0; ls < kSrLog; ls += 2) {
+    const int lt2 = kSrLog - ls - 2;  // log2 t2
+    const int m = 1 << ls;
+    const int g = u >> lt2, i = u & ((1 << lt2) - 1);
+    const int a = (g << (lt2 + 2)) + i, t2 = 1 << lt2;
+    uint32_t x0 = s[a], x1 = s[a + t2], x2 = s[a + 2 * t2], x3 = s[a + 3 * t2];
+    const uint2 w = tw[m + g], w0 = tw[2 * m + 2 * g], w1 = tw[2 * m + 2 * g + 1];
+    bfly_ct(x0, x2, w.x, w.y, q, q2);
+    bfly_ct(x1, x3, w.x, w.y, q, q2);
+    bfly_ct(x0, x1, w0.x, w0.y, q, q2);
+    bfly_ct(x2, x3, w1.x, w1.y, q, q2);
+    s[a] = x0;
+    s[a + t2] = x1;
+    s[a + 2 * t2] = x2;
+    s[a + 3 * t2] = x3;
+    __syncthreads();
+  }
+}
+
+// Inverse (Gentleman-Sande, bit-reversed in, natural out, no N^-1), six
+// radix-4 phases: unit u of the phase on half-sizes (t, 2t) covers
+// a = 4 g t + i, a + t, a + 2t, a + 3t (g = u / t, i = u % t); the stage of
+// m = N / (2t) groups pairs (a, a + t) and (a + 2t, a + 3t), the next
+// (a, a + 2t) and (a + t, a + 3t).  Words in [0, 2q) throughout.
+__device__ __forceinline__ void sr_intt(uint32_t* s, const uint2* itw, uint32_t q) {
+  const uint32_t q2 = 2 * q;
+  const int u = threadIdx.x;
+#pragma unroll
+  for (int lt = 0; lt < kSrLog; lt += 2) {
+    const int m = kSrN >> (lt + 1);
+    const int g = u >> lt, i = u & ((1 << lt) - 1);
+    const int a = (g << (lt + 2)) + i, t = 1 << lt;
+    uint32_t x0 = s[a], x1 = s[a + t], x2 = s[a + 2 * t], x3 = s[a + 3 * t];
+    const uint2 w0 = itw[m + 2 * g], w1 = itw[m + 2 * g + 1], w = itw[(m >> 1) + g];
+    bfly_gs(x0, x1, w0.x, w0.y, q, q2);
+    bfly_gs(x2, x3, w1.x, w1.y, q, q2);
+    bfly_gs(x0, x2, w.x, w.y, q, q2);
+    bfly_gs(x1, x3, w.x, w.y, q, q2);
+    s[a] = x0;
+    s[a + t] = x1;
+    s[a + 2 * t] = x2;
+    s[a + 3 * t] = x3;
+    __syncthreads();
+  }
+}
+
+// The quad at 4 threadIdx.x of row r of the polynomial a job key-switches
+// (evaluation domain): d, c1 c1' or sigma(c1).  Loaded raw (both factors of
+// the product) so that a prefetch does not wait for its data; the product is
+// taken by sr_switched_finish where the quad is used.
+struct SrRaw {
+  uint4 x, y;
+};
+// Branch-free (the kind selects addresses, every load is issued): a load in
+// a branch whose value merges after it makes the compiler wait for it there.
+// x: row r of d, the evaluations of c1 (HMult) or sigma(c1) gathered (HRot);
+// y: row r of c1' (HMult; otherwise x's row again, unused).
+__device__ __forceinline__ SrRaw sr_switched_load(const KsJob& J, int r) {
+  const size_t N = kSrN;
+  const uint32_t n = 4 * threadIdx.x;
+  const bool rot = J.kind == KS_HROT;
+  const uint32_t* src = J.a + (size_t)(J.kind == KS_PLAIN ? r : J.L + r) * N;
+  const uint32_t* src2 = J.kind == KS_HMULT ? J.b + (size_t)(J.L + r) * N : src;
+  SrRaw o;
+  o.x = make_uint4(ld1(src + (rot ? auto_src(n, J.gal, kSrLog) : n)),
+                   ld1(src + (rot ? auto_src(n + 1, J.gal, kSrLog) : n + 1)),
+                   ld1(src + (rot ? auto_src(n + 2, J.gal, kSrLog) : n + 2)),
+                   ld1(src + (rot ? auto_src(n + 3, J.gal, kSrLog) : n + 3)));
+  o.y = ld4(src2 + n);
+  return o;
+}
+__device__ __forceinline__ uint4 sr_switched_finish(const KsJob& J, const SrRaw& v, const ModC& m) {
+  if (J.kind != KS_HMULT) return v.x;
+  return make_uint4(mulmod(v.x.x, v.y.x, m), mulmod(v.x.y, v.y.y, m), mulmod(v.x.z, v.y.z, m),
+                    mulmod(v.x.w, v.y.w, m));
+}
+
+// A thread's four twiddle pairs of a whole-limb table (words t, t + T, t + 2T, t + 3T).
+__device__ __forceinline__ void sr_load_tw(uint2 w[4], const uint2* __restrict__ src) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = src[threadIdx.x + k * kSrT];
+}
+__device__ __forceinline__ void sr_put_tw(uint2* dst, const uint2 w[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) dst[threadIdx.x + k * kSrT] = w[k];
+}
+
+// S1.  The work-group's items are its digits' limbs in order (a digit row of
+// the switched polynomial is one item without transforms).  Every load of
+// an item -- its quad of the switched polynomial, its prime's inverse
+// twiddles and BConv constants, the digit's key words -- is issued before
+// the previous item's transforms, so a work-group waits on memory once at
+// its start and not again.
+__global__ __launch_bounds__(kSrT) void s1_modup_ip(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const int L = J.L, R = L + K.k, beta = (L + K.alpha - 1) / K.alpha;
+  const int t = blockIdx.x, per = sr_per(beta), gi = blockIdx.y;
+  const int j0 = gi * per, j1 = min(beta, j0 + per);
+  if (t >= R || j0 >= beta || J.kind > KS_HROT) return;
+  __shared__ __align__(16) uint32_t sd[kSrN];
+  __shared__ uint2 stw[kSrN], sitw[kSrN];
+  const size_t N = kSrN;
+  const size_t KR = (size_t)K.T.L_max + K.k;
+  const int pt = ks_pidx(t, L, K.T.L_max);
+  const ModC mt = ldc(K.T.mod + pt);
+  const uint32_t n = 4 * threadIdx.x;
+  // the first item of digit j: its first limb, or row t itself when t is one of the digit's rows
+  auto first_limb = [&](int j) { return (t >= j * K.alpha && t < min(j * K.alpha + K.alpha, L)) ? t : j * K.alpha; };
+  auto key_of = [&](int j, uint4& e0, uint4& e1) {
+    const uint32_t* k0 = J.key + ((size_t)j * 2 * KR + pt) * N + n;
+    e0 = ld4(k0);
+    e1 = ld4(k0 + KR * N);
+  };
+  // BConv constants of limb i of digit j: N^-1 (D_j / q_i)^-1 and [D_j / q_i]_{q_t}
+  auto consts_of = [&](int j, int i, uint2& sc, uint64_t& T) {
+    sc = ldc(K.modup_scale + (size_t)L * K.T.L_max + i);
+    T = ldc(K.modup_T + ldc(K.modup_T_off + (size_t)L * K.beta_max + j) + (size_t)t * K.alpha + (i - j * K.alpha));
+  };
+  int j = j0, i = first_limb(j0);
+  SrRaw x = sr_switched_load(J, i);
+  uint4 e0, e1;
+  uint2 iw[4], sc, fw[4];
+  uint64_t T;
+  key_of(j, e0, e1);
+  sr_load_tw(iw, K.T.full_itw(i));  // i < L: a Q prime's table
+  consts_of(j, i, sc, T);
+  sr_load_tw(fw, K.T.full_tw(pt));  // forward twiddles of q_t, issued last: their wait covers the rest
+  sr_put_tw(stw, fw);               // published by the first barrier
+  uint64_t a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
+  uint64_t z0 = 0, z1 = 0, z2 = 0, z3 = 0;
+  for (;;) {
+    const int hi = min(j * K.alpha + K.alpha, L);
+    const bool own = i == t;
+    const bool last_of_digit = own || i == hi - 1;
+    int jn = j, in = i + 1;  // the next item
+    if (last_of_digit) {
+      jn = j + 1;
+      in = jn < j1 ? first_limb(jn) : -1;
+    }
+    // the next item's loads; the registers are written only when there is
+    // one (a load left in flight at the end would hold the wave until it lands)
+    SrRaw xn;
+    uint4 e0n, e1n;
+    uint2 iwn[4], scn;
+    uint64_t Tn;
+    if (in >= 0) {
+      xn = sr_switched_load(J, in);
+      key_of(jn, e0n, e1n);
+      sr_load_tw(iwn, K.T.full_itw(in));  // a Q prime's table (in < L)
+      consts_of(jn, in, scn, Tn);
+    }
+    uint4 v;
+    bool have_v = false;
+    if (own) {
+      v = sr_switched_finish(J, x, mt);
+      have_v = true;
+    } else {
+      const ModC mi = ldc(K.T.mod + i);
+      const uint4 xi = sr_switched_finish(J, x, mi);
+      __syncthreads();  // the previous transform has been read out of LDS
+      sr_put_tw(sitw, iw);
+      *reinterpret_cast<uint4*>(sd + n) = xi;
+      __syncthreads();
+      sr_intt(sd, sitw, mi.q);
+      const uint4 y = *reinterpret_cast<const uint4*>(sd + n);
+      z0 += (uint64_t)csub(mul_shoup(y.x, sc.x, sc.y, mi.q), mi.q) * T;
+      z1 += (uint64_t)csub(mul_shoup(y.y, sc.x, sc.y, mi.q), mi.q) * T;
+      z2 += (uint64_t)csub(mul_shoup(y.z, sc.x, sc.y, mi.q), mi.q) * T;
+      z3 += (uint64_t)csub(mul_shoup(y.w, sc.x, sc.y, mi.q), mi.q) * T;
+      if (last_of_digit) {  // the digit's sum, mod q_t, transformed forward
+        __syncthreads();
+        *reinterpret_cast<uint4*>(sd + n) =
+            make_uint4(reduce64(z0, mt.q, mt.mu_hi, mt.mu_lo), reduce64(z1, mt.q, mt.mu_hi, mt.mu_lo),
+                       reduce64(z2, mt.q, mt.mu_hi, mt.mu_lo), reduce64(z3, mt.q, mt.mu_hi, mt.mu_lo));
+        z0 = z1 = z2 = z3 = 0;
+        __syncthreads();
+        sr_ntt(sd, stw, mt.q);
+        v = canon4(*reinterpret_cast<const uint4*>(sd + n), mt.q, 2 * mt.q);
+        have_v = true;
+      }
+    }
+    if (have_v) {
+      a0[0] += (uint64_t)v.x * e0.x;
+      a0[1] += (uint64_t)v.y * e0.y;
+      a0[2] += (uint64_t)v.z * e0.z;
+      a0[3] += (uint64_t)v.w * e0.w;
+      a1[0] += (uint64_t)v.x * e1.x;
+      a1[1] += (uint64_t)v.y * e1.y;
+      a1[2] += (uint64_t)v.z * e1.z;
+      a1[3] += (uint64_t)v.w * e1.w;
+      if (((j - j0) & 7) == 7) {  // canonical products < 2^60: fold every eighth digit
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          a0[e] = reduce64(a0[e], mt.q, mt.mu_hi, mt.mu_lo);
+          a1[e] = reduce64(a1[e], mt.q, mt.mu_hi, mt.mu_lo);
+        }
+      }
+    }
+    if (in < 0) break;
+    j = jn;
+    i = in;
+    x = xn;
+    e0 = e0n;
+    e1 = e1n;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) iw[k] = iwn[k];
+    sc = scn;
+    T = Tn;
+  }
+  uint32_t* p0 = J.ws + ((size_t)(2 * gi) * R + t) * N + n;
+  uint32_t* p1 = p0 + (size_t)R * N;
+  st4(p0, make_uint4(reduce64(a0[0], mt.q, mt.mu_hi, mt.mu_lo), reduce64(a0[1], mt.q, mt.mu_hi, mt.mu_lo),
+                     reduce64(a0[2], mt.q, mt.mu_hi, mt.mu_lo), reduce64(a0[3], mt.q, mt.mu_hi, mt.mu_lo)));
+  st4(p1, make_uint4(reduce64(a1[0], mt.q, mt.mu_hi, mt.mu_lo), reduce64(a1[1], mt.q, mt.mu_hi, mt.mu_lo),
+                     reduce64(a1[2], mt.q, mt.mu_hi, mt.mu_lo), reduce64(a1[3], mt.q, mt.mu_hi, mt.mu_lo)));
+}
+
+// The groups' partials (at most four) at the thread's quad of row r, loaded
+// raw: group indices past `groups` repeat the last group and are dropped by
+// sr_partials_sum.
+__device__ __forceinline__ void sr_partials_load(uint4 v[4], const uint32_t* ws, int groups, int c, int R, int r) {
+  const size_t N = kSrN;
+  const uint32_t n = 4 * threadIdx.x;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) v[g] = ld4(ws + ((size_t)(2 * min(g, groups - 1) + c) * R + r) * N + n);
+}
+__device__ __forceinline__ uint4 sr_partials_sum(const uint4 v[4], int groups, uint32_t q) {
+  uint4 s = v[0];  // canonical partials: the sum of four stays below 4q < 2^32
+#pragma unroll
+  for (int g = 1; g < 4; ++g) {
+    const uint32_t k = g < groups ? 0xffffffffu : 0u;
+    s.x += v[g].x & k;
+    s.y += v[g].y & k;
+    s.z += v[g].z & k;
+    s.w += v[g].w & k;
+  }
+  return canon4(s, q, 2 * q);
+}
+
+// S2.  Every load is issued at the start (the next P row's during the
+// current P row's transform): q_i's forward twiddles, the accumulator's
+// partials at row i, the epilogue operands, the first P row's partials and
+// inverse twiddles.
+__global__ __launch_bounds__(kSrT) void s2_moddown(KsConst K, JobArg<KsJob> JA) {
+  const KsJob J = JA.get(blockIdx.z);
+  const int L = J.L, R = L + K.k, beta = (L + K.alpha - 1) / K.alpha;
+  const int i = blockIdx.x, c = blockIdx.y, groups = sr_groups(beta);
+  if (i >= L || J.kind > KS_HROT) return;
+  __shared__ __align__(16) uint32_t sd[kSrN];
+  __shared__ uint2 stw[kSrN], sitw[kSrN];
+  const size_t N = kSrN, Lz = L;
+  const uint32_t n = 4 * threadIdx.x;
+  const ModC mi = ldc(K.T.mod + i);
+  const uint32_t q = mi.q, q2 = 2 * q;
+  uint2 fw[4], iw[4];
+  sr_load_tw(fw, K.T.full_tw(i));
+  uint4 pa[4], px[4];
+  sr_partials_load(px, J.ws, groups, c, R, L);
+  sr_load_tw(iw, K.T.full_itw(K.T.L_max));
+  sr_partials_load(pa, J.ws, groups, c, R, i);
+  // the epilogue operands, branch-free (as in sr_switched_load): c0, c0', c1,
+  // c1' at row i (HMult: c0 c0' / c0 c1' + c1 c0'); sigma(c0) gathered (HRot, c = 0)
+  const bool hm = J.kind == KS_HMULT, rot = J.kind == KS_HROT && c == 0;
+  const uint32_t* ra = J.a + i * N;
+  const uint32_t* rb = hm ? J.b + i * N : ra;
+  const uint32_t* rc = hm ? J.a + (Lz + i) * N : ra;
+  const uint32_t* rd = hm ? J.b + (Lz + i) * N : ra;
+  const uint4 ea = make_uint4(ld1(ra + (rot ? auto_src(n, J.gal, kSrLog) : n)),
+                              ld1(ra + (rot ? auto_src(n + 1, J.gal, kSrLog) : n + 1)),
+                              ld1(ra + (rot ? auto_src(n + 2, J.gal, kSrLog) : n + 2)),
+                              ld1(ra + (rot ? auto_src(n + 3, J.gal, kSrLog) : n + 3)));
+  const uint4 eb = ld4(rb + n), ec = ld4(rc + n), ed = ld4(rd + n);
+  sr_put_tw(stw, fw);  // published by the first barrier below
+  // ModDown: w = sum_m x_m [P / p_m]_{q_i}, x_m = INTT(acc P row m) N^-1 (P / p_m)^-1
+  uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+  for (int mm = 0; mm < K.k; ++mm) {
+    const int pm = K.T.L_max + mm;
+    const ModC mp = ldc(K.T.mod + pm);
+    const uint2 sc = ldc(K.moddown_scale + mm);
+    const uint64_t T = ldc(K.moddown_T + (size_t)i * K.k + mm);
+    const bool more = mm + 1 < K.k;
+    uint4 pxn[4];
+    uint2 iwn[4];
+    if (more) {  // the next P row's loads
+      sr_partials_load(pxn, J.ws, groups, c, R, L + mm + 1);
+      sr_load_tw(iwn, K.T.full_itw(pm + 1));
+    }
+    const uint4 x = sr_partials_sum(px, groups, mp.q);
+    __syncthreads();  // the previous P row has been read out of LDS
+    sr_put_tw(sitw, iw);
+    *reinterpret_cast<uint4*>(sd + n) = x;
+    __syncthreads();
+    sr_intt(sd, sitw, mp.q);
+    const uint4 y = *reinterpret_cast<const uint4*>(sd + n);
+    w0 += (uint64_t)csub(mul_shoup(y.x, sc.x, sc.y, mp.q), mp.q) * T;
+    w1 += (uint64_t)csub(mul_shoup(y.y, sc.x, sc.y, mp.q), mp.q) * T;
+    w2 += (uint64_t)csub(mul_shoup(y.z, sc.x, sc.y, mp.q), mp.q) * T;
+    w3 += (uint64_t)csub(mul_shoup(y.w, sc.x, sc.y, mp.q), mp.q) * T;
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        px[k] = pxn[k];
+        iw[k] = iwn[k];
+      }
+    }
+  }
+  const uint2 pv = ldc(K.pinv + i);
+  __syncthreads();
+  *reinterpret_cast<uint4*>(sd + n) = make_uint4(reduce64(w0, q, mi.mu_hi, mi.mu_lo), reduce64(w1, q, mi.mu_hi, mi.mu_lo),
+                                                 reduce64(w2, q, mi.mu_hi, mi.mu_lo), reduce64(w3, q, mi.mu_hi, mi.mu_lo));
+  __syncthreads();
+  sr_ntt(sd, stw, q);
+  const uint4 w = csub4(*reinterpret_cast<const uint4*>(sd + n), q2);  // [0, 2q)
+  const uint4 a = sr_partials_sum(pa, groups, q);
+  uint4 d = rot ? ea : make_uint4(0, 0, 0, 0);
+  if (hm) {
+    if (c == 0) {
+      d = make_uint4(mulmod(ea.x, eb.x, mi), mulmod(ea.y, eb.y, mi), mulmod(ea.z, eb.z, mi), mulmod(ea.w, eb.w, mi));
+    } else {
+      d = make_uint4(reduce64((uint64_t)ea.x * ed.x + (uint64_t)ec.x * eb.x, q, mi.mu_hi, mi.mu_lo),
+                     reduce64((uint64_t)ea.y * ed.y + (uint64_t)ec.y * eb.y, q, mi.mu_hi, mi.mu_lo),
+                     reduce64((uint64_t)ea.z * ed.z + (uint64_t)ec.z * eb.z, q, mi.mu_hi, mi.mu_lo),
+                     reduce64((uint64_t)ea.w * ed.w + (uint64_t)ec.w * eb.w, q, mi.mu_hi, mi.mu_lo));
+    }
+  }
+  const uint32_t o0 = csub(mul_shoup(a.x + q2 - w.x, pv.x, pv.y, q), q);
+  const uint32_t o1 = csub(mul_shoup(a.y + q2 - w.y, pv.x, pv.y, q), q);
+  const uint32_t o2 = csub(mul_shoup(a.z + q2 - w.z, pv.x, pv.y, q), q);
+  const uint32_t o3 = csub(mul_shoup(a.w + q2 - w.w, pv.x, pv.y, q), q);
+  st4(J.out + ((size_t)c * Lz + i) * N + n, make_uint4(csub(o0 + d.x, q), csub(o1 + d.y, q), csub(o2 + d.z, q), csub(o3 + d.w, q)));
+}
 }  // namespace
 
 size_t ks_ws_words(const Ctx& c, int L) {
@@ -1436,6 +1797,16 @@ hipError_t ks_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, con
   const int down_rows = sc.down_rows == 2 || sc.down_rows == 4 || sc.down_rows == 6 ? sc.down_rows : 12;
   const int down_groups = (Lmax + down_rows - 1) / down_rows;
   hipError_t e;
+  if constexpr (L1 + kBlockLog == kSrLog) {
+    // small ring: two kernels on whole limbs (plain, HMult and HRot jobs)
+    if ((sc.ntt_shape & kShapeWholeLimb) && with_modup && !with_hoist && !sp.side) {
+      const int bmax = c.beta(Lmax);
+      const int per = (bmax + 3) / 4;
+      klaunch_b(c, CKKS_STAGE_NTT_IP, s1_modup_ip, dim3(Rmax, (bmax + per - 1) / per, njobs), kSrT, st, K, jobs);
+      klaunch_b(c, CKKS_STAGE_NTT_COMBINE, s2_moddown, dim3(Lmax, 2, njobs), kSrT, st, K, jobs);
+      return hipGetLastError();
+    }
+  }
   if (with_modup && (e = modup_stage_t<L1>(c, sc, K, jobs, njobs, Lmax, st)) != hipSuccess) return e;
   // Stage 2.  With a side stream, complementary pipelining (Sec. IV-B): the
   // inner product of the P rows runs on st and ModDown's P-row chain (K6..K8,

@@ -110,6 +110,9 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
   std::vector<uint2> tw((size_t)nP * N1), itw((size_t)nP * N1);
   std::vector<uint2> ctw((size_t)nP * 256), ictw((size_t)nP * 256);
   std::vector<uint2> twist((size_t)nP * N1 * 32), itwist((size_t)nP * N1 * 32);
+  // whole-limb tables of small rings: all N entries of the bit-reversed table
+  const bool small_ring = c.logN == kSrLog;
+  std::vector<uint2> ftw(small_ring ? (size_t)nP * N : 0), fitw(small_ring ? (size_t)nP * N : 0);
   for (int i = 0; i < nP; ++i) {
     const u64 qi = c.primes[i];
     const u64 psi = min_root(qi, N), psii = invm(psi, qi);
@@ -124,6 +127,12 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
       tw[(size_t)i * N1 + e] = shoup(powm(psi, b, qi), qi);
       itw[(size_t)i * N1 + e] = shoup(powm(psii, b, qi), qi);
     }
+    if (small_ring)
+      for (u64 e = 0; e < N; ++e) {
+        const uint32_t b = brv((uint32_t)e, c.logN);
+        ftw[(size_t)i * N + e] = shoup(powm(psi, b, qi), qi);
+        fitw[(size_t)i * N + e] = shoup(powm(psii, b, qi), qi);
+      }
     // block pass (twisted): index 2^s + g -> psi^((N / 2^s) brv_s(g))
     ctw[(size_t)i * 256] = ictw[(size_t)i * 256] = shoup(1, qi);
     for (int s = 0; s < 8; ++s)
@@ -234,6 +243,10 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
   if (!(err = upload(&c.d_ictw, ictw, code)).empty()) return err;
   if (!(err = upload(&c.d_twist, twist, code)).empty()) return err;
   if (!(err = upload(&c.d_itwist, itwist, code)).empty()) return err;
+  if (small_ring) {
+    if (!(err = upload(&c.d_ftw, ftw, code)).empty()) return err;
+    if (!(err = upload(&c.d_fitw, fitw, code)).empty()) return err;
+  }
   if (!(err = upload(&c.d_modup_scale, mscale, code)).empty()) return err;
   if (!(err = upload(&c.d_modup_T, mT, code)).empty()) return err;
   std::vector<uint32_t> toff(c.modup_T_off.begin(), c.modup_T_off.end());
@@ -247,7 +260,8 @@ std::string build_tables(Ctx& c, const uint32_t* q, const uint32_t* p, int* code
 }
 
 void free_tables(Ctx& c) {
-  void* ptrs[] = {c.d_mod, c.d_tw, c.d_itw, c.d_ctw, c.d_ictw, c.d_twist, c.d_itwist, c.d_modup_scale, c.d_modup_T, c.d_modup_T_off,
+  void* ptrs[] = {c.d_mod, c.d_tw, c.d_itw, c.d_ctw, c.d_ictw, c.d_twist, c.d_itwist, c.d_ftw, c.d_fitw,
+                  c.d_modup_scale, c.d_modup_T, c.d_modup_T_off,
                   c.d_moddown_scale, c.d_moddown_T, c.d_pinv, c.d_rescale_inv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

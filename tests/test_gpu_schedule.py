@@ -13,8 +13,9 @@ from gpu_helpers import dev, empty, first_mismatch, host
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
+# ntt_shape 8..15 (whole-limb key-switch) act at N = 2^12 only
 SCHEDULES = [(12, 6, 128, 0), (4, 4, 0, 1), (6, 12, 512, 2), (2, 2, 0, 3), (4, 6, 65535, 4), (2, 12, 1024, 5),
-             (12, 4, 128, 6), (6, 2, 0, 7)]
+             (12, 4, 128, 6), (6, 2, 0, 7), (12, 6, 128, 8), (4, 4, 0, 13)]
 FIELDS = ("bconv_up_rows", "bconv_down_rows", "small_grid", "ntt_shape")
 
 
@@ -49,15 +50,16 @@ def test_every_schedule_matches_the_oracle(name, L):
         msg = first_mismatch(host(out), want_m)
         assert not msg, f"tuned schedule {best}: {msg}"
     finally:
-        P.ckks_ctx_set_schedule(h, 12, 6, 128)
+        P.ckks_ctx_set_schedule(h, 12, 6, 128, 8 if spec.logN == 12 else 0)
 
 
 def test_bad_schedules_are_rejected():
     ctx = P.Context.from_spec(ci.get("n12_l4"))
-    for sch in [(5, 6, 128), (12, 8, 128), (1, 6, 128), (12, 6, -1), (12, 6, 70000), (12, 6, 128, 8),
+    for sch in [(5, 6, 128), (12, 8, 128), (1, 6, 128), (12, 6, -1), (12, 6, 70000), (12, 6, 128, 16),
                 (12, 6, 128, -1)]:
         with pytest.raises(P.CkksError) as e:
             P.ckks_ctx_set_schedule(ctx.handle, *sch)
         assert e.value.code == -1
+    # N = 2^12: the whole-limb key-switch by default
     assert P.ckks_ctx_get_schedule(ctx.handle) == dict(bconv_up_rows=12, bconv_down_rows=6, small_grid=128,
-                                                       ntt_shape=0)
+                                                       ntt_shape=8)
