@@ -149,6 +149,20 @@ int ckks_tensor(const ckks_ctx *ctx, const uint32_t *ct1, const uint32_t *ct2, i
 int ckks_pmult_sum(const ckks_ctx *ctx, const uint32_t *const *h_cts, const uint32_t *const *h_pts,
                    int nb, int L, uint32_t *out, void *stream);
 
+/*
+ * Several inner sums over the same ciphertexts in one launch (the giant steps
+ * of one BSGS level, Sec. II-B3): out_g[c][i] = sum_{b < nb} ct_b[c][i] *
+ * pt_{g,b}[i] mod q_i for g < ng, each ciphertext word read once for all ng
+ * sums.  h_cts: nb device pointers to [2][L][N] ciphertexts; h_pts: ng * nb
+ * device pointers to [L][N] evaluation-domain plaintexts, group-major
+ * (pt_{g,b} at h_pts[g * nb + b]); h_outs: ng device pointers to [2][L][N]
+ * outputs, none aliasing an input or each other.  1 <= nb <= 16,
+ * 1 <= ng <= 8.  Each out_g equals ckks_pmult_sum of the same ciphertexts and
+ * group g's plaintexts.
+ */
+int ckks_pmult_sums(const ckks_ctx *ctx, const uint32_t *const *h_cts, int nb, const uint32_t *const *h_pts,
+                    int ng, int L, uint32_t *const *h_outs, void *stream);
+
 /* Ciphertext sum (element-wise): out = a + b over [2][L][N]; out may alias a or b. */
 int ckks_add(const ckks_ctx *ctx, const uint32_t *a, const uint32_t *b, int L, uint32_t *out,
              void *stream);

@@ -22,7 +22,7 @@ __all__ = [
     "ckks_batch_destroy", "ckks_batch_plan", "ckks_batch_get_plan", "ckks_batch_set_plan",
     "ckks_batch_tune", "ckks_batch_tune_log", "ckks_stats", "ckks_server_create", "ckks_server_submit",
     "ckks_server_poll", "ckks_server_drain", "ckks_server_set_accounting", "ckks_server_stats", "ckks_server_times",
-    "ckks_server_destroy", "ckks_pmult_sum", "ckks_add", "ckks_schedule", "ckks_ctx_get_schedule",
+    "ckks_server_destroy", "ckks_pmult_sum", "ckks_pmult_sums", "ckks_add", "ckks_schedule", "ckks_ctx_get_schedule",
     "ckks_ctx_set_schedule", "ckks_ctx_tune", "ckks_batch_get_schedule", "ckks_batch_set_schedule",
 ]
 
@@ -118,6 +118,7 @@ _SIGS = {
     "ckks_batch_tune": [_vp, _i, _vp, _vp, _vp],
     "ckks_batch_tune_log": [_vp, _vp, _vp, _i, ctypes.POINTER(_i)],
     "ckks_pmult_sum": [_vp, _vp, _vp, _i, _i, _vp, _vp],
+    "ckks_pmult_sums": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp],
     "ckks_add": [_vp, _vp, _vp, _i, _vp, _vp],
     "ckks_server_create": [_vp, _i, _sz, _i, ctypes.POINTER(_vp)],
     "ckks_server_submit": [_vp, _i, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
@@ -364,6 +365,18 @@ def ckks_pmult_sum(ctx, cts, pts, L, out, stream=None):
     b = (_vp * n)(*[_ptr(t) for t in pts])
     _check(lib().ckks_pmult_sum(ctx, ctypes.cast(a, _vp), ctypes.cast(b, _vp), n, L, _ptr(out),
                                 _stream(stream)))
+
+
+def ckks_pmult_sums(ctx, cts, pt_groups, L, outs, stream=None):
+    """outs[g] = sum_b cts[b] * pt_groups[g][b]; every group has len(cts) plaintexts."""
+    nb, ng = len(cts), len(pt_groups)
+    if any(len(grp) != nb for grp in pt_groups) or len(outs) != ng:
+        raise CkksError(-1, "pmult_sums: one plaintext per ciphertext in every group, one output per group")
+    a = (_vp * nb)(*[_ptr(t) for t in cts])
+    b = (_vp * (ng * nb))(*[_ptr(t) for grp in pt_groups for t in grp])
+    o = (_vp * ng)(*[_ptr(t) for t in outs])
+    _check(lib().ckks_pmult_sums(ctx, ctypes.cast(a, _vp), nb, ctypes.cast(b, _vp), ng, L, ctypes.cast(o, _vp),
+                                 _stream(stream)))
 
 
 def ckks_add(ctx, a, b, L, out, stream=None):

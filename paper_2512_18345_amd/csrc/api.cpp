@@ -451,6 +451,24 @@ int ckks_pmult_sum(const ckks_ctx* ctx, const uint32_t* const* h_cts, const uint
   return CKKS_OK;
 }
 
+int ckks_pmult_sums(const ckks_ctx* ctx, const uint32_t* const* h_cts, int nb, const uint32_t* const* h_pts,
+                    int ng, int L, uint32_t* const* h_outs, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!h_cts || !h_pts || !h_outs || nb < 1 || nb > 16 || ng < 1 || ng > 8)
+    return fail(CKKS_EINVAL, "bad pmult_sums arguments (1 <= nb <= 16, 1 <= ng <= 8)");
+  for (int b = 0; b < nb; ++b)
+    if (!h_cts[b]) return fail(CKKS_EINVAL, "null ciphertext pointer");
+  for (int g = 0; g < ng; ++g) {
+    if (!h_outs[g]) return fail(CKKS_EINVAL, "null output pointer");
+    for (int b = 0; b < nb; ++b)
+      if (!h_pts[g * nb + b]) return fail(CKKS_EINVAL, "null plaintext pointer");
+  }
+  DeviceGuard g(ctx->c.device);
+  CKKS_TRY(launch_pmult_sums(ctx->c, h_cts, nb, h_pts, ng, L, h_outs, (hipStream_t)stream), "pmult_sums");
+  return CKKS_OK;
+}
+
 int ckks_add(const ckks_ctx* ctx, const uint32_t* a, const uint32_t* b, int L, uint32_t* out,
              void* stream) {
   int rc = check_level(ctx, L);

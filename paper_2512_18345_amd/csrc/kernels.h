@@ -35,6 +35,8 @@ hipError_t launch_sub_scale(const Ctx& c, int rows, const uint32_t* a, const uin
 
 hipError_t launch_pmult_sum(const Ctx& c, const uint32_t* const* cts, const uint32_t* const* pts, int nb,
                             int L, uint32_t* out, hipStream_t st);
+hipError_t launch_pmult_sums(const Ctx& c, const uint32_t* const* cts, int nb, const uint32_t* const* pts,
+                             int ng, int L, uint32_t* const* outs, hipStream_t st);
 hipError_t launch_ct_add(const Ctx& c, const uint32_t* a, const uint32_t* b, int L, uint32_t* out,
                          hipStream_t st);
 

@@ -302,6 +302,54 @@ __global__ __launch_bounds__(kWG) void k_pmult_sum(DevTab T, PtrList16 cts, PtrL
                  reduce64(a1[2], m.q, m.mu_hi, m.mu_lo), reduce64(a1[3], m.q, m.mu_hi, m.mu_lo)));
 }
 
+// Several inner sums over the same ciphertexts (the giant steps of one BSGS
+// level): out_g[c][i] = sum_b ct_b[c][i] * pt_{g,b}[i] mod q_i for g < NG.
+// Each ciphertext word is read once for all NG sums.
+struct PtrList128 {
+  const uint32_t* p[128];
+};
+struct OutList8 {
+  uint32_t* p[8];
+};
+template <int NG>
+__global__ __launch_bounds__(kWG) void k_pmult_sums(DevTab T, PtrList16 cts, PtrList128 pts, OutList8 outs,
+                                                    int nb, int L) {
+  const size_t N = (size_t)1 << T.logN;
+  const size_t n = ((size_t)blockIdx.x * kWG + threadIdx.x) * 4;  // four coefficients per thread
+  const int i = blockIdx.y;
+  const ModC m = ldc(T.mod + i);
+  uint64_t a0[NG][4], a1[NG][4];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a0[g][e] = a1[g][e] = 0;
+  for (int b = 0; b < nb; ++b) {
+    const uint4 x = ld4(cts.p[b] + (size_t)i * N + n);
+    const uint4 y = ld4(cts.p[b] + ((size_t)L + i) * N + n);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const uint4 pt = ld4(pts.p[g * 16 + b] + (size_t)i * N + n);
+      a0[g][0] += (uint64_t)x.x * pt.x;
+      a0[g][1] += (uint64_t)x.y * pt.y;
+      a0[g][2] += (uint64_t)x.z * pt.z;
+      a0[g][3] += (uint64_t)x.w * pt.w;
+      a1[g][0] += (uint64_t)y.x * pt.x;
+      a1[g][1] += (uint64_t)y.y * pt.y;
+      a1[g][2] += (uint64_t)y.z * pt.z;
+      a1[g][3] += (uint64_t)y.w * pt.w;
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    st4(outs.p[g] + (size_t)i * N + n,
+        make_uint4(reduce64(a0[g][0], m.q, m.mu_hi, m.mu_lo), reduce64(a0[g][1], m.q, m.mu_hi, m.mu_lo),
+                   reduce64(a0[g][2], m.q, m.mu_hi, m.mu_lo), reduce64(a0[g][3], m.q, m.mu_hi, m.mu_lo)));
+    st4(outs.p[g] + ((size_t)L + i) * N + n,
+        make_uint4(reduce64(a1[g][0], m.q, m.mu_hi, m.mu_lo), reduce64(a1[g][1], m.q, m.mu_hi, m.mu_lo),
+                   reduce64(a1[g][2], m.q, m.mu_hi, m.mu_lo), reduce64(a1[g][3], m.q, m.mu_hi, m.mu_lo)));
+  }
+}
+
 // Ciphertext sum: out = a + b over [2][L][N].
 __global__ __launch_bounds__(kWG) void k_ct_add(DevTab T, const uint32_t* a, const uint32_t* b, int L,
                                                 uint32_t* out) {
@@ -426,6 +474,31 @@ hipError_t launch_pmult_sum(const Ctx& c, const uint32_t* const* cts, const uint
     b.p[i] = pts[i];
   }
   k_pmult_sum<<<dim3(c.N / (4 * kWG), L), kWG, 0, st>>>(c.tab(), a, b, nb, L, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pmult_sums(const Ctx& c, const uint32_t* const* cts, int nb, const uint32_t* const* pts,
+                             int ng, int L, uint32_t* const* outs, hipStream_t st) {
+  if (nb < 1 || nb > 16 || ng < 1 || ng > 8) return hipErrorInvalidValue;
+  PtrList16 a{};
+  PtrList128 b{};
+  OutList8 o{};
+  for (int j = 0; j < nb; ++j) a.p[j] = cts[j];
+  for (int g = 0; g < ng; ++g) {
+    o.p[g] = outs[g];
+    for (int j = 0; j < nb; ++j) b.p[g * 16 + j] = pts[g * nb + j];
+  }
+  const dim3 grid(c.N / (4 * kWG), L);
+  switch (ng) {
+    case 1: k_pmult_sums<1><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+    case 2: k_pmult_sums<2><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+    case 3: k_pmult_sums<3><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+    case 4: k_pmult_sums<4><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+    case 5: k_pmult_sums<5><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+    case 6: k_pmult_sums<6><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+    case 7: k_pmult_sums<7><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+    default: k_pmult_sums<8><<<grid, kWG, 0, st>>>(c.tab(), a, b, o, nb, L); break;
+  }
   return hipGetLastError();
 }
 

@@ -3,7 +3,7 @@
 Shape (the linear transforms of bootstrapping around a multiplication
 chain, on uniform residues):  three linear-transform levels, each = one
 hoisted group of 16 baby-step rotations sharing one ModUp, four inner sums
-of 16 plaintext products, four giant-step rotations, their sum and a
+of 16 plaintext products (one launch), four giant-step rotations, their sum and a
 rescale; a chain of 12 squarings (HMult) with rescales; three more
 linear-transform levels.  132 key-switches; L drops 36 -> 33 -> 21 -> 18 at
 the default parameters.  Every step is a library call on the given stream.
@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import torch
 
-from . import (ckks_add, ckks_hmult, ckks_hrot, ckks_hrot_hoisted, ckks_pmult_sum,
+from . import (ckks_add, ckks_hmult, ckks_hrot, ckks_hrot_hoisted, ckks_pmult_sums,
                ckks_rescale)
 
 
@@ -34,11 +34,14 @@ def run(ctx, ct, L, shape, rotkeys, rlk, pts, stream=None):
         baby, giant = shape["baby"], shape["giant"]
         rotated = [empty(2, L, N) for _ in baby]
         ckks_hrot_hoisted(h, ct, L, baby, [rotkeys[r] for r in baby], rotated, ws["HROT_HOISTED"], stream)
+        # every giant step's inner sum in one launch, each rotated ciphertext read once
+        inners = [empty(2, L, N) for _ in giant]
+        groups = [[p[:L] for p in pts[g * len(baby):(g + 1) * len(baby)]] for g in range(len(giant))]
+        for g0 in range(0, len(giant), 8):  # at most eight sums per launch
+            ckks_pmult_sums(h, rotated, groups[g0:g0 + 8], L, inners[g0:g0 + 8], stream)
         acc = None
         for g, rg in enumerate(giant):
-            group = pts[g * len(baby):(g + 1) * len(baby)]
-            inner = empty(2, L, N)
-            ckks_pmult_sum(h, rotated, [p[:L] for p in group], L, inner, stream)
+            inner = inners[g]
             out = empty(2, L, N)
             ckks_hrot(h, inner, L, rg, rotkeys[rg], out, ws["HROT"], stream)
             if acc is None:

@@ -64,3 +64,45 @@ def test_pmult_sum_and_add_against_oracle():
     s = torch.empty_like(out)
     P.ckks_add(ctx.handle, dev(cts[0]), dev(cts[1]), L, s)
     assert not first_mismatch(host(s), O.ct_add(par, cts[0], cts[1], L))
+
+
+@pytest.mark.parametrize("name,L,nb,ng", [("n16_l36", 30, 16, 4), ("n16_l36", 36, 3, 8), ("n12_l4", 4, 16, 1),
+                                          ("n12_l4", 3, 5, 7)])
+def test_pmult_sums_equal_single_sums_and_the_oracle(name, L, nb, ng):
+    """Several giant steps' inner sums in one launch: each output equals the
+    oracle's inner sum of its group and, bitwise, ckks_pmult_sum of the same
+    ciphertexts and plaintexts."""
+    spec = ci.get(name)
+    par = O.Params.from_spec(spec)
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(23 + ng)
+    cts = [rng.polys(2, spec.q[:L], spec.N) for _ in range(nb)]
+    groups = [[rng.residues(spec.q[:L], spec.N) for _ in range(nb)] for _ in range(ng)]
+    d_cts = [dev(c) for c in cts]
+    d_groups = [[dev(p) for p in grp] for grp in groups]
+    outs = [torch.full((2, L, spec.N), -1, dtype=torch.int32, device="cuda") for _ in range(ng)]
+    P.ckks_pmult_sums(ctx.handle, d_cts, d_groups, L, outs)
+    for g in range(ng):
+        single = torch.empty_like(outs[g])
+        P.ckks_pmult_sum(ctx.handle, d_cts, d_groups[g], L, single)
+        got = host(outs[g])
+        assert not first_mismatch(got, host(single)), f"group {g}: differs from ckks_pmult_sum"
+        msg = first_mismatch(got, O.pmult_sum(par, cts, groups[g], L))
+        assert not msg, f"group {g}: {msg}"
+
+
+def test_pmult_sums_rejects_bad_counts():
+    spec = ci.get("n12_l4")
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(5)
+    ct = dev(rng.polys(2, spec.q, spec.N))
+    pt = dev(rng.residues(spec.q, spec.N))
+    out = [torch.empty((2, spec.L_max, spec.N), dtype=torch.int32, device="cuda") for _ in range(9)]
+    with pytest.raises(P.CkksError) as e:
+        P.ckks_pmult_sums(ctx.handle, [ct], [[pt]] * 9, spec.L_max, out)  # nine groups
+    assert e.value.code == -1
+    with pytest.raises(P.CkksError) as e:
+        P.ckks_pmult_sums(ctx.handle, [ct] * 17, [[pt] * 17], spec.L_max, out[:1])  # 17 products
+    assert e.value.code == -1
+    with pytest.raises(P.CkksError):
+        P.ckks_pmult_sums(ctx.handle, [ct, ct], [[pt]], spec.L_max, out[:1])  # group of the wrong size
