@@ -464,7 +464,9 @@ def batched_numbers(P, ci, ctx, spec, d_rlk, reps):
 
 def boot_trace_numbers(runs):
     """The bootstrapping-shaped trace at N=2^16 from L=36 (2^15 slots): one run
-    to warm up, then `runs` timed runs; ms per trace and key-switches/s."""
+    to warm up, then `runs` timed runs; ms per trace and key-switches/s, eager
+    and as one captured hipGraph replayed (its output checked bitwise against
+    the eager run's)."""
     import torch
     import ckks_inputs as ci
     import paper_2512_18345_amd as P
@@ -488,9 +490,26 @@ def boot_trace_numbers(runs):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / runs
     nks = trace.key_switches(shape)
+    # the same trace captured once as a hipGraph (stream capture through torch,
+    # intermediates in the graph's pool) and replayed: one submission per trace
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gout, _ = trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts)
+    graph.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(gout, out))
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        graph.replay()
+    torch.cuda.synchronize()
+    gdt = (time.perf_counter() - t0) / runs
+    same = same and bool(torch.equal(gout, out))
+    del graph
     ctx.close()
     return {"ms_per_trace": round(dt * 1e3, 3), "key_switches": nks, "ks_per_s": round(nks / dt, 1),
-            "L_start": spec.L_max, "L_end": Lf, "runs": runs}
+            "L_start": spec.L_max, "L_end": Lf, "runs": runs,
+            "graph_ms_per_trace": round(gdt * 1e3, 3), "graph_ks_per_s": round(nks / gdt, 1),
+            "graph_equals_eager": same}
 
 
 def serve_numbers(n_requests, budget_gib, sweep_budgets):

@@ -106,3 +106,37 @@ def test_pmult_sums_rejects_bad_counts():
     assert e.value.code == -1
     with pytest.raises(P.CkksError):
         P.ckks_pmult_sums(ctx.handle, [ct, ct], [[pt]], spec.L_max, out[:1])  # group of the wrong size
+
+
+def test_boot_trace_captured_as_one_graph_replays_exactly():
+    """The whole trace captured once into a hipGraph (every library call on the
+    capture stream, intermediates in the graph's pool) and replayed three times,
+    with eager work in between: every replay equals the eager run bitwise."""
+    spec = ci.get("boot_trace_n12")
+    shape = ci.BOOT_TRACE
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(spec.seed + 7)
+    L = spec.L_max
+    ct = dev(rng.polys(2, spec.q, spec.N))
+    rots = sorted(set(shape["baby"]) | set(shape["giant"]))
+    keys = {r: dev(rng.evk(spec)) for r in rots}
+    rlk = dev(rng.evk(spec))
+    pts = [dev(rng.residues(spec.q, spec.N)) for _ in range(len(shape["baby"]) * len(shape["giant"]))]
+    want, Lw = trace.run(ctx, ct, L, shape, keys, rlk, pts)
+    torch.cuda.synchronize()
+    want = want.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        got, Lg = trace.run(ctx, ct, L, shape, keys, rlk, pts)
+    assert Lg == Lw
+    for rep in range(3):
+        print(f"replay {rep}", flush=True)
+        got.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        msg = first_mismatch(host(got), host(want))
+        assert not msg, f"replay {rep}: {msg}"
+        again, _ = trace.run(ctx, ct, L, shape, keys, rlk, pts)  # eager work between replays
+        torch.cuda.synchronize()
+        assert not first_mismatch(host(again), host(want))
+    del graph
