@@ -1262,12 +1262,13 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
 //       INTT whole in LDS, their conversion to q_i, its NTT -- combined with
 //       the accumulator, plus the job's epilogue term.
 // The arithmetic is that of the nine kernels (exact: the same residues).
-// Scratch of a job: the partials [groups][2][L + k][N] (at most 4 groups).
+// Scratch of a job: the partials [groups][2][L + k][N] (at most kSrGroups = 4).
 // ============================================================================
 constexpr int kSrN = 1 << kSrLog;
 constexpr int kSrT = kSrN / 4;  // threads: one radix-4 unit / one quad each
 
-__device__ __forceinline__ int sr_per(int beta) { return (beta + 3) >> 2; }  // digits per group
+constexpr int kSrGroups = 4;  // digit groups of s1, at most (partial accumulators)
+__device__ __forceinline__ int sr_per(int beta) { return (beta + kSrGroups - 1) / kSrGroups; }  // digits per group
 __device__ __forceinline__ int sr_groups(int beta) { return (beta + sr_per(beta) - 1) / sr_per(beta); }
 
 // Forward negacyclic NTT of the limb in s (natural coefficients in,
@@ -1800,9 +1801,10 @@ hipError_t ks_launch_t(const Ctx& c, const Ctx::Sched& sc, const KsConst& K, con
   if constexpr (L1 + kBlockLog == kSrLog) {
     // small ring: two kernels on whole limbs (plain, HMult and HRot jobs)
     if ((sc.ntt_shape & kShapeWholeLimb) && with_modup && !with_hoist && !sp.side) {
-      const int bmax = c.beta(Lmax);
-      const int per = (bmax + 3) / 4;
-      klaunch_b(c, CKKS_STAGE_NTT_IP, s1_modup_ip, dim3(Rmax, (bmax + per - 1) / per, njobs), kSrT, st, K, jobs);
+      // every job splits its own digits into sr_groups(beta) <= min(beta, kSrGroups)
+      // groups, so the grid covers min(bmax, kSrGroups) (not the largest job's count)
+      const int groups = std::min(c.beta(Lmax), kSrGroups);
+      klaunch_b(c, CKKS_STAGE_NTT_IP, s1_modup_ip, dim3(Rmax, groups, njobs), kSrT, st, K, jobs);
       klaunch_b(c, CKKS_STAGE_NTT_COMBINE, s2_moddown, dim3(Lmax, 2, njobs), kSrT, st, K, jobs);
       return hipGetLastError();
     }

@@ -223,3 +223,42 @@ def test_graph_batch_rejects_several_branches():
                          "established, so graph batches run one branch (set_plan rejects streams > 1)")
 def test_graph_multi_branch_plans():
     _check_plans(True, [(0, 2, 1), (1, 4, 1), (2, 3, 0), (3, 2, 1)])
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_small_ring_batch_of_uneven_digit_counts(use_graph):
+    """At N = 2^12 a key-switch is two whole-limb kernels whose first splits each
+    job's digits into at most four groups.  Jobs of one launch with different
+    digit counts (digit size 1: 3 to 9 digits) -- e.g. a 4-digit job beside a
+    5-, 6- or 9-digit one, where the largest job alone would need only three
+    groups -- must each equal their single call, and one equals the oracle."""
+    spec = ci.get("n12_l24_k1")
+    ctx = P.Context.from_spec(spec)
+    par = O.Params.from_spec(spec)
+    rng = ci.Rng(spec.seed + 400)
+    keys = [dev(rng.evk(spec))]
+    # two launches' worth of level mixes: largest beta 5, 6 and 9 with a beta-4 or beta-8 job beside it
+    levels = [5, 4, 3, 6, 4, 9, 8, 4]
+    jobs, singles = _make_jobs(spec, ctx, rng, len(levels), levels, keys)
+    want = [_single(ctx, *s) for s in singles]
+    b = P.ckks_batch_create(ctx.handle, jobs, use_graph=use_graph)
+    try:
+        # unsplit plans take the whole-limb kernels (a split plan runs the nine-kernel pipeline)
+        for plan in [None, (0, 1, 0), (3, 1, 0)]:
+            print(f"plan {plan} graph={use_graph}", flush=True)
+            if plan:
+                P.ckks_batch_set_plan(b, *plan)
+            for rep in range(2):
+                for j in jobs:
+                    j["out"].fill_(-1)
+                P.ckks_batch_launch(b)
+                torch.cuda.synchronize()
+                for i, j in enumerate(jobs):
+                    msg = first_mismatch(host(j["out"]), want[i])
+                    assert not msg, f"plan {plan}, replay {rep}, job {i} ({singles[i][0]}, L={singles[i][1]}): {msg}"
+    finally:
+        P.ckks_batch_destroy(b)
+    op, L, rot, ct1, ct2, key = singles[1]  # HROT at L = 4 beside larger jobs
+    assert op == "HROT" and L == 4
+    msg = first_mismatch(want[1], O.hrot(par, host(ct1), L, rot, host(key)))
+    assert not msg, f"single HRot vs oracle: {msg}"
