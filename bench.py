@@ -19,6 +19,7 @@ the CPU oracle timed on a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import subprocess
@@ -493,8 +494,13 @@ def boot_trace_numbers(runs):
     # the same trace captured once as a hipGraph (stream capture through torch,
     # intermediates in the graph's pool) and replayed: one submission per trace
     graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        gout, _ = trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts)
+    gc.collect()  # no destructor (a freed context's hipFree) may run inside the capture
+    gc.disable()
+    try:
+        with torch.cuda.graph(graph):
+            gout, _ = trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts)
+    finally:
+        gc.enable()
     graph.replay()
     torch.cuda.synchronize()
     same = bool(torch.equal(gout, out))

@@ -103,7 +103,10 @@ const char *ckks_last_error(void);
  * sum_j T[i][j] * Q_j < 2^64 of Sec. III-C2 for every table.
  * Errors: CKKS_EINVAL (bad primes / sizes), CKKS_EUNSUPPORTED (logN or
  * L_max + k out of range, bound violated), CKKS_ENOMEM, CKKS_EHIP.
- * Owns device memory until ckks_ctx_destroy.
+ * Owns device memory until ckks_ctx_destroy.  ckks_ctx_destroy frees device
+ * memory (hipFree): it must not run while a stream capture is in progress
+ * (it would invalidate the capture).  The single-operation entry points
+ * launch kernels only on the given stream, so they may be captured.
  */
 int ckks_ctx_create(ckks_ctx **out, int logN, const uint32_t *h_q, int L_max,
                     const uint32_t *h_p, int k, int dnum, int device);

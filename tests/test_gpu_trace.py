@@ -3,6 +3,8 @@ plaintext inner sums, giant-step rotations, rescales, a squaring chain) run
 through the C-ABI, checked bit-exact against the same composition of oracle
 steps: at the workload's own size (N=2^16, 36 + 12 primes, dnum 3) and with
 the same shape and chain on a 2^12 ring."""
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -126,8 +128,15 @@ def test_boot_trace_captured_as_one_graph_replays_exactly():
     torch.cuda.synchronize()
     want = want.clone()
     graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        got, Lg = trace.run(ctx, ct, L, shape, keys, rlk, pts)
+    # no destructor may run inside the capture: a context freed by the garbage
+    # collector there (hipFree) would invalidate it
+    gc.collect()
+    gc.disable()
+    try:
+        with torch.cuda.graph(graph):
+            got, Lg = trace.run(ctx, ct, L, shape, keys, rlk, pts)
+    finally:
+        gc.enable()
     assert Lg == Lw
     for rep in range(3):
         print(f"replay {rep}", flush=True)
