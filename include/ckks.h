@@ -367,7 +367,10 @@ int ckks_batch_launch(ckks_batch *batch, void *stream);
  * starts it beside the P-row inner product, split = 2 after it, so that it
  * overlaps only the P-row ModDown chain.
  * Rescale jobs run on the last branch.  Every plan gives bitwise the same
- * results.  Default {0, 1, 1}; {0, 1, 0} for a batch of one key-switching job.  A batch created with use_graph runs one
+ * results.  Default {0, 1, 1}; {0, 1, 0} for a batch of one key-switching
+ * job, and at N = 2^12 under the whole-limb schedule (ntt_shape bit 8) while
+ * (L + k) * min(beta, 4) * jobs <= 800 for its largest level L (split runs
+ * the nine-kernel pipeline, which pays off only past that).  A batch created with use_graph runs one
  * branch (streams = 1): a multi-branch launch sequence is not captured.
  */
 typedef struct ckks_batch_plan {

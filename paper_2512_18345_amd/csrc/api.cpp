@@ -770,8 +770,15 @@ int ckks_batch_create(const ckks_ctx* ctx, const ckks_job* h_jobs, int n, int us
   b->use_graph = use_graph != 0;
   b->sched = ctx->c.sched;
   // complementary pipelining pays off only when a launch group holds several
-  // jobs; a lone key-switch runs unsplit, as a single call does
-  b->plan.split = b->n_ks >= 2 ? 1 : 0;
+  // jobs; a lone key-switch runs unsplit, as a single call does.  On a small
+  // ring with the whole-limb schedule the unsplit launch (two kernels) is the
+  // faster one until its first kernel needs about 800 work-groups: HMults at
+  // N = 2^12, L = 4 (20 work-groups each) measured 1.4-2.3x faster unsplit for
+  // 2-32 jobs and even at 48.
+  const int Lks = ks.empty() ? 0 : ks[order[0]].L;
+  const bool whole_limb = c.logN == kSrLog && (b->sched.ntt_shape & kShapeWholeLimb);
+  const long sr_wgs = (long)(Lks + c.k) * std::min(c.beta(std::max(Lks, 1)), kSrGroups) * b->n_ks;
+  b->plan.split = b->n_ks >= 2 && !(whole_limb && sr_wgs <= 800) ? 1 : 0;
   const size_t tab = round_up(sizeof(KsJob) * ks.size()) + round_up(sizeof(RsJob) * rs.size());
   if (hipMalloc(&b->d_ws, ws) != hipSuccess ||
       (!ks.empty() && hipMalloc(&b->d_ks, sizeof(KsJob) * ks.size()) != hipSuccess) ||

@@ -51,6 +51,7 @@ constexpr int kShapeInvRadix16 = 2;  // inverse column passes: 16 elements / thr
 constexpr int kShapeK1Radix16 = 4;   // ModUp INTT block pass: 16 elements / thread on 256 threads (else 8 on 512)
 constexpr int kShapeWholeLimb = 8;   // N = 2^kSrLog: two kernels with whole limbs in LDS instead of nine
 constexpr int kShapeAll = 15;
+constexpr int kSrGroups = 4;  // whole-limb key-switch: digit groups of its first kernel, at most
 
 // Rows of the key inner product a K5 launch covers.
 enum KsPart : int { KS_PART_ALL = 0, KS_PART_P = 1, KS_PART_Q = 2 };

@@ -1267,7 +1267,6 @@ __global__ __launch_bounds__(kWG) void r4_ntt_blks_combine(KsConst K, JobArg<RsJ
 constexpr int kSrN = 1 << kSrLog;
 constexpr int kSrT = kSrN / 4;  // threads: one radix-4 unit / one quad each
 
-constexpr int kSrGroups = 4;  // digit groups of s1, at most (partial accumulators)
 __device__ __forceinline__ int sr_per(int beta) { return (beta + kSrGroups - 1) / kSrGroups; }  // digits per group
 __device__ __forceinline__ int sr_groups(int beta) { return (beta + sr_per(beta) - 1) / sr_per(beta); }
 

@@ -57,9 +57,9 @@ def _single(ctx, op, L, rot, ct1, ct2, key):
     return host(out)
 
 
-# n12_l4 with 40 jobs: at N = 2^12 the launches of a large batch take the
-# whole-tile shapes (radix-8 K1 and column passes, the staged K5), which small
-# single calls never reach
+# n12_l4 with 40 jobs: at N = 2^12 the split launches of a large batch take the
+# nine-kernel pipeline's whole-tile shapes (radix-8 K1 and column passes, the
+# staged K5), which small single calls never reach
 @pytest.mark.parametrize("name,n,use_graph", [("n12_l4", 9, True), ("n12_l4", 40, True), ("n16_l36", 12, True),
                                                ("n16_l36", 6, False)])
 def test_batch_equals_single_calls(name, n, use_graph):
@@ -72,15 +72,21 @@ def test_batch_equals_single_calls(name, n, use_graph):
     b = P.ckks_batch_create(ctx.handle, jobs, use_graph=use_graph)
     try:
         want = [_single(ctx, *s) for s in singles]
-        for rep in range(3):  # graph replays with eager work and syncs in between
-            for j in jobs:
-                j["out"].fill_(-1)
-            P.ckks_batch_launch(b)
-            torch.cuda.synchronize()
-            for i, j in enumerate(jobs):
-                msg = first_mismatch(host(j["out"]), want[i])
-                assert not msg, f"replay {rep}, job {i} ({singles[i][0]}, L={singles[i][1]}): {msg}"
-            _ = _single(ctx, *singles[0])
+        # at N = 2^12 the default plan is unsplit (two whole-limb kernels); the
+        # split plan runs the nine-kernel pipeline's whole-tile shapes
+        plans = [None, (0, 1, 1)] if spec.logN == 12 else [None]
+        for plan in plans:
+            if plan:
+                P.ckks_batch_set_plan(b, *plan)
+            for rep in range(3):  # graph replays with eager work and syncs in between
+                for j in jobs:
+                    j["out"].fill_(-1)
+                P.ckks_batch_launch(b)
+                torch.cuda.synchronize()
+                for i, j in enumerate(jobs):
+                    msg = first_mismatch(host(j["out"]), want[i])
+                    assert not msg, f"plan {plan} replay {rep}, job {i} ({singles[i][0]}, L={singles[i][1]}): {msg}"
+                _ = _single(ctx, *singles[0])
     finally:
         P.ckks_batch_destroy(b)
 
@@ -262,3 +268,22 @@ def test_small_ring_batch_of_uneven_digit_counts(use_graph):
     assert op == "HROT" and L == 4
     msg = first_mismatch(want[1], O.hrot(par, host(ct1), L, rot, host(key)))
     assert not msg, f"single HRot vs oracle: {msg}"
+
+
+def test_small_ring_default_plan_depends_on_the_batch_size():
+    """At N = 2^12 (whole-limb schedule) a batch runs unsplit until the first
+    kernel's grid passes 800 work-groups ((L + k) min(beta, 4) per job): 40
+    HMults at L = 4 (800) stay unsplit, 41 split."""
+    spec = ci.get("n12_l4")
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(9)
+    ct = dev(rng.polys(2, spec.q, spec.N))
+    key = dev(rng.evk(spec))
+    out = empty(2, spec.L_max, spec.N)
+    for n, split in ((1, 0), (2, 0), (40, 0), (41, 1)):
+        jobs = [dict(op=P.JOB["HMULT"], L=spec.L_max, in0=ct, in1=ct, key=key, out=out) for _ in range(n)]
+        b = P.ckks_batch_create(ctx.handle, jobs, use_graph=False)
+        try:
+            assert P.ckks_batch_get_plan(b)["split"] == split, f"{n} jobs"
+        finally:
+            P.ckks_batch_destroy(b)
