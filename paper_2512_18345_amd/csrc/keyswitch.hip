@@ -1367,11 +1367,11 @@ __device__ __forceinline__ void sr_put_tw(uint2* dst, const uint2 w[4]) {
 }
 
 // S1.  The work-group's items are its digits' limbs in order (a digit row of
-// the switched polynomial is one item without transforms).  Every load of
-// an item -- its quad of the switched polynomial, its prime's inverse
-// twiddles and BConv constants, the digit's key words -- is issued before
-// the previous item's transforms, so a work-group waits on memory once at
-// its start and not again.
+// the switched polynomial is one item without transforms).  The loads of an
+// item -- its quad of the switched polynomial, its prime's inverse twiddles
+// and BConv constants, the digit's key words -- are issued one item ahead,
+// before the current item's transforms, so only the first item waits on
+// memory.
 __global__ __launch_bounds__(kSrT) void s1_modup_ip(KsConst K, JobArg<KsJob> JA) {
   const KsJob J = JA.get(blockIdx.z);
   const int L = J.L, R = L + K.k, beta = (L + K.alpha - 1) / K.alpha;
