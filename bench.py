@@ -158,7 +158,7 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
               "(batch-level data parallelism across GPUs needs no collective and is not run here).",
               file=sys.stderr)
         sys.exit(2)

@@ -55,7 +55,7 @@ def test_bconv_is_crt_plus_small_multiple_of_D():
 def test_bconv_overflow_bound_matches_paper_example():
     """Sec. III-C2: with L_in = 12 moduli near 2^31 the accumulator can reach
     about 3 * 2^64 (the size bound L_in * 2^31 * 2^31), and the real table
-    of such a chain does overflow 64 bits; with this build's chain (< 2^30)
+    of such a chain does overflow 64 bits; with the library's chain (< 2^30)
     sum_j T[i][j] * Q_j stays below 2^64, so one final reduction suffices."""
     g = _read_golden("bconv_bound.txt")
     l_in = int(g["l_in"])
