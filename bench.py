@@ -15,6 +15,7 @@ the CPU oracle timed on a bounded sample on the host cores.
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
     python bench.py --boot-trace      # the bootstrapping-shaped trace alone, more runs
     python bench.py --serve           # the serving loop alone, with an HBM-budget sweep
+    python bench.py --batched         # the batched comparison alone
 """
 from __future__ import annotations
 
@@ -119,6 +120,8 @@ def parse():
                     help="HBM budgets (GiB) of the extra saturated serving runs (--serve)")
     ap.add_argument("--boot-trace", action="store_true",
                     help="only run the bootstrapping-shaped operation trace (132 key-switches)")
+    ap.add_argument("--batched", action="store_true",
+                    help="only run the batched comparison (8 HMults; the 64-job mixed batch)")
     ap.add_argument("--serve", action="store_true",
                     help="only run the serving-loop benchmark (Poisson arrivals, p50/p99, budget sweep)")
     ap.add_argument("--serve-requests", type=int, default=300)
@@ -194,6 +197,10 @@ def main():
     out_r = torch.empty((2, L, N), dtype=torch.int32, device="cuda")
     out_s = torch.empty((2, L - 1, N), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+
+    if args.batched:
+        print(json.dumps({"batched": batched_numbers(P, ci, ctx, spec, d_rlk, args.batch_reps)}), flush=True)
+        return
 
     # kernel schedule picked by the library's autotuner (before any timing)
     schedule = None
