@@ -65,12 +65,13 @@ def test_bad_schedules_are_rejected():
                                                        ntt_shape=8)
 
 
-@pytest.mark.parametrize("logN,L", [(13, 7), (14, 13)])
-def test_every_ntt_shape_at_n13_n14(logN, L):
-    """The column- and block-pass shapes compiled for N = 2^13 and 2^14 (the
+@pytest.mark.parametrize("logN,L", [(13, 7), (14, 13), (15, 20)])
+def test_every_ntt_shape_at_n13_n14_n15(logN, L):
+    """The column- and block-pass shapes compiled for N = 2^13 .. 2^15 (the
     36 + 12 chain at these degrees): HMult under each NTT shape and BConv
-    schedule, hoisted rotations, and a mixed-level batch, against the oracle
-    or the single calls."""
+    schedule (bit 8, the whole-limb key-switch, acts at N = 2^12 only and is
+    ignored here), hoisted rotations, and a mixed-level batch, against the
+    oracle or the single calls."""
     base = ci.get("n16_l36")
     spec = ci.ChainSpec(base.name, logN, base.q, base.p, base.dnum, base.seed)
     par = O.Params.from_spec(spec)
@@ -82,7 +83,8 @@ def test_every_ntt_shape_at_n13_n14(logN, L):
     d1, d2, dk = dev(ct1), dev(ct2), dev(key)
     want = O.hmult(par, ct1, ct2, L, key)
     try:
-        for sch in [(12, 6, 128, s) for s in range(8)] + [(2, 4, 0, 0), (6, 12, 65535, 3)]:
+        for sch in [(12, 6, 128, s) for s in range(8)] + [(2, 4, 0, 0), (6, 12, 65535, 3), (12, 6, 128, 8),
+                                                          (4, 4, 128, 13)]:
             P.ckks_ctx_set_schedule(h, *sch)
             out = empty(2, L, N)
             P.ckks_hmult(h, d1, d2, L, dk, out, ctx.workspace("HMULT", L))
