@@ -283,8 +283,9 @@ int ckks_rescale(const ckks_ctx *ctx, const uint32_t *ct, int L, uint32_t *out, 
  *                    key-switch as two kernels that hold whole limbs in
  *                    LDS (ModUp + inner product per row and digit group,
  *                    ModDown + epilogue per output row) instead of the
- *                    nine-kernel pipeline.  Small grids keep their own
- *                    shapes.  0..15.
+ *                    nine-kernel pipeline (hoisted rotations and batch
+ *                    plans with a split inner product keep the nine
+ *                    kernels).  Small grids keep their own shapes.  0..15.
  * Default {12, 6, 128, 0}; {12, 6, 128, 8} for N = 2^12.  The schedule is read when work is enqueued (and when
  * a graph batch is captured); changing it must not overlap calls on the
  * context.  Every schedule gives bitwise the same results.
