@@ -221,3 +221,41 @@ def test_whole_footprint_budget_covers_inputs_outputs_and_keys(contexts):
         for i, j in enumerate(batch):
             msg = first_mismatch(host(j["out"]), _alone(ctx, j))
             assert not msg, f"budget {budget}: job {i}: {msg}"
+
+
+def test_small_ring_jobs_in_the_mix():
+    """At N = 2^12 the server's launches take the two whole-limb kernels over
+    jobs of different digit counts (digit size 1, levels 3..12): every result
+    equals the job run alone, and a sample of four equals the oracle."""
+    spec = ci.get("n12_l24_k1")
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(81)
+    key = dev(rng.evk(spec))
+    jobs = []
+    for i in range(40):
+        L = int(rng.integers(3, 13))
+        op = ["KEYSWITCH", "HMULT", "HROT", "RESCALE"][i % 4]
+        ct1 = dev(rng.polys(2, spec.q[:L], spec.N))
+        ct2 = dev(rng.polys(2, spec.q[:L], spec.N))
+        if op == "KEYSWITCH":
+            job = dict(op=P.JOB[op], L=L, in0=ct1[0], key=key, out=empty(2, L, spec.N))
+        elif op == "RESCALE":
+            job = dict(op=P.JOB[op], L=L, in0=ct1, out=empty(2, L - 1, spec.N))
+        else:
+            job = dict(op=P.JOB[op], L=L, rot=rng.rotation(spec.N), in0=ct1,
+                       in1=ct2 if op == "HMULT" else None, key=key, out=empty(2, L, spec.N))
+        jobs.append(job)
+    srv = P.ckks_server_create([ctx.handle], 2 << 30, 16)
+    try:
+        for j in jobs:
+            P.ckks_server_submit(srv, 0, j)
+        P.ckks_server_drain(srv)
+        assert P.ckks_server_stats(srv)["completed"] == len(jobs)
+    finally:
+        P.ckks_server_destroy(srv)
+    for i, j in enumerate(jobs):
+        msg = first_mismatch(host(j["out"]), _alone(ctx, j))
+        assert not msg, f"job {i} (op {j['op']}, L={j['L']}): {msg}"
+    for i in (1, 2, 5, 7):
+        msg = first_mismatch(host(jobs[i]["out"]), _oracle(spec, jobs[i]))
+        assert not msg, f"job {i} vs oracle: {msg}"
