@@ -241,6 +241,20 @@ int ckks_hrot(const ckks_ctx *ctx, const uint32_t *ct, int L, int rot, const uin
               uint32_t *out, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Several independent rotations in one launch sequence (the giant steps of a
+ * BSGS level, Sec. II-B3 and Fig. keysw): out_i = HRot(ct_i, rot_i) under key
+ * rotk_i for i < n, exactly as n ckks_hrot calls, but every pipeline kernel
+ * covers all n jobs (Sec. IV-A batching).  h_cts, h_rotks, h_outs: n device
+ * pointers each (ciphertexts and outputs [2][L][N], keys as for ckks_hrot);
+ * h_rots: n rotation amounts (host array); 1 <= n <= 16; no output may alias
+ * an input or another output.  ws: n times ckks_workspace_bytes(ctx,
+ * CKKS_OP_HROT, L) bytes (CKKS_ENOMEM if smaller).  Errors as ckks_hrot.
+ */
+int ckks_hrot_many(const ckks_ctx *ctx, const uint32_t *const *h_cts, int L, const int *h_rots,
+                   const uint32_t *const *h_rotks, uint32_t *const *h_outs, int n, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/*
  * Hoisted rotations (rotations reordered so that one ModUp is shared;
  * Sec. V-C): M = ModUp(c1) once; for each n: sigma_{g_n} on every row of M
  * (Q and P), inner product with h_rotks[n], ModDown, plus sigma_{g_n}(c0).

@@ -22,7 +22,7 @@ __all__ = [
     "ckks_batch_destroy", "ckks_batch_plan", "ckks_batch_get_plan", "ckks_batch_set_plan",
     "ckks_batch_tune", "ckks_batch_tune_log", "ckks_stats", "ckks_server_create", "ckks_server_submit",
     "ckks_server_poll", "ckks_server_drain", "ckks_server_set_accounting", "ckks_server_stats", "ckks_server_times",
-    "ckks_server_destroy", "ckks_pmult_sum", "ckks_pmult_sums", "ckks_add", "ckks_schedule", "ckks_ctx_get_schedule",
+    "ckks_server_destroy", "ckks_pmult_sum", "ckks_pmult_sums", "ckks_hrot_many", "ckks_add", "ckks_schedule", "ckks_ctx_get_schedule",
     "ckks_ctx_set_schedule", "ckks_ctx_tune", "ckks_batch_get_schedule", "ckks_batch_set_schedule",
 ]
 
@@ -119,6 +119,7 @@ _SIGS = {
     "ckks_batch_tune_log": [_vp, _vp, _vp, _i, ctypes.POINTER(_i)],
     "ckks_pmult_sum": [_vp, _vp, _vp, _i, _i, _vp, _vp],
     "ckks_pmult_sums": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp],
+    "ckks_hrot_many": [_vp, _vp, _i, _vp, _vp, _vp, _i, _vp, _sz, _vp],
     "ckks_add": [_vp, _vp, _vp, _i, _vp, _vp],
     "ckks_server_create": [_vp, _i, _sz, _i, ctypes.POINTER(_vp)],
     "ckks_server_submit": [_vp, _i, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)],
@@ -367,6 +368,21 @@ def ckks_pmult_sum(ctx, cts, pts, L, out, stream=None):
                                 _stream(stream)))
 
 
+def ckks_hrot_many(ctx, cts, L, rots, rotks, outs, ws, stream=None):
+    """outs[i] = HRot(cts[i], rots[i]) under rotks[i], one launch sequence; ws holds
+    len(cts) times the HRot workspace."""
+    n = len(cts)
+    if len(rots) != n or len(rotks) != n or len(outs) != n:
+        raise CkksError(-1, "hrot_many: one rotation, key and output per ciphertext")
+    a = (_vp * n)(*[_ptr(t) for t in cts])
+    r = (_i * n)(*[int(x) for x in rots])
+    k = (_vp * n)(*[_ptr(t) for t in rotks])
+    o = (_vp * n)(*[_ptr(t) for t in outs])
+    w, nb = _ws(ws)
+    _check(lib().ckks_hrot_many(ctx, ctypes.cast(a, _vp), L, ctypes.cast(r, _vp), ctypes.cast(k, _vp),
+                                ctypes.cast(o, _vp), n, w, nb, _stream(stream)))
+
+
 def ckks_pmult_sums(ctx, cts, pt_groups, L, outs, stream=None):
     """outs[g] = sum_b cts[b] * pt_groups[g][b]; every group has len(cts) plaintexts."""
     nb, ng = len(cts), len(pt_groups)
@@ -467,9 +483,10 @@ class Context:
     def beta(self, L: int) -> int:
         return -(-L // self.alpha)
 
-    def workspace(self, op: str, L: int):
+    def workspace(self, op: str, L: int, count: int = 1):
+        """Device workspace for `count` jobs of `op` at level L (count > 1: ckks_hrot_many)."""
         import torch
-        nb = ckks_workspace_bytes(self.handle, OP[op], L)
+        nb = ckks_workspace_bytes(self.handle, OP[op], L) * count
         return torch.empty(max(nb // 4, 1), dtype=torch.int32, device=f"cuda:{self.device}")
 
     def close(self):

@@ -570,6 +570,32 @@ int ckks_hrot(const ckks_ctx* ctx, const uint32_t* ct, int L, int rot, const uin
   return run_one(c, KS_HROT, L, galois(c, rot), ct, nullptr, rotk, out, ws, (hipStream_t)stream);
 }
 
+int ckks_hrot_many(const ckks_ctx* ctx, const uint32_t* const* h_cts, int L, const int* h_rots,
+                   const uint32_t* const* h_rotks, uint32_t* const* h_outs, int n, void* ws,
+                   size_t ws_bytes_given, void* stream) {
+  int rc = check_level(ctx, L);
+  if (rc) return rc;
+  if (!h_cts || !h_rots || !h_rotks || !h_outs || n < 1 || n > kInlineJobs)
+    return fail(CKKS_EINVAL, "bad rotation-list arguments (1 <= n <= 16)");
+  for (int i = 0; i < n; ++i)
+    if (!h_cts[i] || !h_rotks[i] || !h_outs[i]) return fail(CKKS_EINVAL, "null ciphertext, key or output pointer");
+  const Ctx& c = ctx->c;
+  const size_t per = ws_bytes(c, CKKS_OP_HROT, L);
+  if (!ws) return fail(CKKS_EINVAL, "null workspace");
+  if (ws_bytes_given < per * n)
+    return fail(CKKS_ENOMEM, "workspace of " + std::to_string(ws_bytes_given) + " bytes < " +
+                                 std::to_string(per * n) + " needed (n times the HRot workspace)");
+  DeviceGuard g(c.device);
+  // the jobs of one launch sequence, each with its own slice of the workspace
+  JobArg<KsJob> ja{};
+  ja.table = nullptr;
+  for (int i = 0; i < n; ++i)
+    ja.inl[i] = KsJob{KS_HROT, L, galois(c, h_rots[i]), 0, h_cts[i], nullptr, h_rotks[i], h_outs[i],
+                      (uint32_t*)((char*)ws + per * i)};
+  CKKS_TRY(ks_launch(c, c.sched, ja, n, L, true, false, (hipStream_t)stream), "key-switching pipeline");
+  return CKKS_OK;
+}
+
 int ckks_hrot_hoisted(const ckks_ctx* ctx, const uint32_t* ct, int L, const int* h_rots, int n,
                       const uint32_t* const* h_rotks, uint32_t* const* h_outs, void* ws,
                       size_t ws_bytes_given, void* stream) {

@@ -14,7 +14,7 @@ import oracle as O
 import paper_2512_18345_amd as P
 from paper_2512_18345_amd import trace
 from compose import oracle_trace
-from gpu_helpers import dev, first_mismatch, host
+from gpu_helpers import dev, empty, first_mismatch, host
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -149,3 +149,43 @@ def test_boot_trace_captured_as_one_graph_replays_exactly():
         torch.cuda.synchronize()
         assert not first_mismatch(host(again), host(want))
     del graph
+
+
+@pytest.mark.parametrize("name,L,n", [("n16_l36", 30, 4), ("n12_l4", 4, 5), ("n12_l24_k1", 9, 3)])
+def test_hrot_many_equals_single_calls_and_the_oracle(name, L, n):
+    """Independent rotations in one launch sequence equal ckks_hrot call by call
+    bitwise (N = 2^12 takes the whole-limb kernels over all jobs), and the
+    first equals the oracle."""
+    spec = ci.get(name)
+    par = O.Params.from_spec(spec)
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(41 + n)
+    cts = [rng.polys(2, spec.q[:L], spec.N) for _ in range(n)]
+    keys = [rng.evk(spec) for _ in range(n)]
+    rots = [rng.rotation(spec.N) for _ in range(n)]
+    d_cts, d_keys = [dev(c) for c in cts], [dev(k) for k in keys]
+    outs = [torch.full((2, L, spec.N), -1, dtype=torch.int32, device="cuda") for _ in range(n)]
+    P.ckks_hrot_many(ctx.handle, d_cts, L, rots, d_keys, outs, ctx.workspace("HROT", L, n))
+    for i in range(n):
+        one = empty(2, L, spec.N)
+        P.ckks_hrot(ctx.handle, d_cts[i], L, rots[i], d_keys[i], one, ctx.workspace("HROT", L))
+        msg = first_mismatch(host(outs[i]), host(one))
+        assert not msg, f"rotation {i}: {msg}"
+    msg = first_mismatch(host(outs[0]), O.hrot(par, cts[0], L, rots[0], keys[0]))
+    assert not msg, f"vs oracle: {msg}"
+
+
+def test_hrot_many_rejects_bad_arguments():
+    spec = ci.get("n12_l4")
+    ctx = P.Context.from_spec(spec)
+    rng = ci.Rng(6)
+    L = spec.L_max
+    ct = dev(rng.polys(2, spec.q, spec.N))
+    key = dev(rng.evk(spec))
+    out = [empty(2, L, spec.N) for _ in range(17)]
+    with pytest.raises(P.CkksError) as e:  # 17 rotations
+        P.ckks_hrot_many(ctx.handle, [ct] * 17, L, [1] * 17, [key] * 17, out, ctx.workspace("HROT", L, 17))
+    assert e.value.code == -1
+    with pytest.raises(P.CkksError) as e:  # workspace for one job only
+        P.ckks_hrot_many(ctx.handle, [ct] * 2, L, [1, 2], [key] * 2, out[:2], ctx.workspace("HROT", L))
+    assert e.value.code == -2
