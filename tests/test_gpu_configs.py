@@ -121,6 +121,23 @@ def _edge_case(name, L, kind, n_hoisted):
         msg = first_mismatch(host(outs[i]), want[i])
         assert not msg, f"{tag} hoisted rotation {i} of {n_hoisted}: {msg}"
 
+    # independent rotations in one launch sequence (extreme key, zero key, extreme key)
+    many = rots[:3]
+    mkeys = [key, zero_key, key]
+    mouts = [empty(2, L, N) for _ in many]
+    P.ckks_hrot_many(h, [d1, d2, d1], L, many, [dk, dz, dk], mouts, ctx.workspace("HROT", L, 3))
+    for i, (c, r, k) in enumerate(zip([ct1, ct2, ct1], many, mkeys)):
+        msg = first_mismatch(host(mouts[i]), O.hrot(par, c, L, r, k))
+        assert not msg, f"{tag} hrot_many rotation {i}: {msg}"
+
+    # sixteen products per inner sum (the 64-bit accumulation's bound), two sums
+    pt = ci.edge_residues(kind, spec.q[:L], N, (pos * 5 + 1) % N)
+    sums = [empty(2, L, N) for _ in range(2)]
+    P.ckks_pmult_sums(h, [d1] * 16, [[dev(pt)] * 16, [dev(ct2[0])] * 16], L, sums)
+    for g, p_ in enumerate((pt, ct2[0])):
+        msg = first_mismatch(host(sums[g]), O.pmult_sum(par, [ct1] * 16, [p_] * 16, L))
+        assert not msg, f"{tag} pmult_sums group {g}: {msg}"
+
     if L >= 2:
         res = empty(2, L - 1, N)
         P.ckks_rescale(h, d1, L, res, ctx.workspace("RESCALE", L))
