@@ -115,7 +115,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--small-reps", type=int, default=10000,
                     help="HMult latency samples at N=2^12, 4+1 primes, dnum 4 (0 = skip)")
-    ap.add_argument("--trace-runs", type=int, default=3, help="timed runs of the trace in the default line")
+    ap.add_argument("--trace-runs", type=int, default=5, help="timed runs of the trace in the default line")
     ap.add_argument("--serve-budgets", type=str, default="0.25,1,64",
                     help="HBM budgets (GiB) of the extra saturated serving runs (--serve)")
     ap.add_argument("--boot-trace", action="store_true",
@@ -471,10 +471,11 @@ def batched_numbers(P, ci, ctx, spec, d_rlk, reps):
 
 
 def boot_trace_numbers(runs):
-    """The bootstrapping-shaped trace at N=2^16 from L=36 (2^15 slots): one run
-    to warm up, then `runs` timed runs; ms per trace and key-switches/s, eager
-    and as one captured hipGraph replayed (its output checked bitwise against
-    the eager run's)."""
+    """The bootstrapping-shaped trace at N=2^16 from L=36 (2^15 slots): two
+    runs to warm up, then `runs` runs each timed on its own (synchronised
+    before and after); ms per trace is their median (min and max beside it),
+    eager and as one captured hipGraph replayed (its output checked bitwise
+    against the eager run's)."""
     import torch
     import ckks_inputs as ci
     import paper_2512_18345_amd as P
@@ -490,13 +491,20 @@ def boot_trace_numbers(runs):
     rlk = _dev(rng.evk(spec))
     pts = [_dev(rng.residues(spec.q, spec.N)) for _ in range(len(shape["baby"]) * len(shape["giant"]))]
     stream = torch.cuda.current_stream()
-    trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts, stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(runs):
-        out, Lf = trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts, stream)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / runs
+
+    def timed(fn):
+        times = []
+        for _ in range(runs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return float(np.median(times)), min(times), max(times), r
+
+    for _ in range(2):
+        trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts, stream)
+    dt, dmin, dmax, (out, Lf) = timed(lambda: trace.run(ctx, ct, spec.L_max, shape, keys, rlk, pts, stream))
     nks = trace.key_switches(shape)
     # the same trace captured once as a hipGraph (stream capture through torch,
     # intermediates in the graph's pool) and replayed: one submission per trace
@@ -511,18 +519,15 @@ def boot_trace_numbers(runs):
     graph.replay()
     torch.cuda.synchronize()
     same = bool(torch.equal(gout, out))
-    t0 = time.perf_counter()
-    for _ in range(runs):
-        graph.replay()
-    torch.cuda.synchronize()
-    gdt = (time.perf_counter() - t0) / runs
+    gdt, gmin, gmax, _ = timed(graph.replay)
     same = same and bool(torch.equal(gout, out))
     del graph
     ctx.close()
-    return {"ms_per_trace": round(dt * 1e3, 3), "key_switches": nks, "ks_per_s": round(nks / dt, 1),
-            "L_start": spec.L_max, "L_end": Lf, "runs": runs,
-            "graph_ms_per_trace": round(gdt * 1e3, 3), "graph_ks_per_s": round(nks / gdt, 1),
-            "graph_equals_eager": same}
+    ms = lambda x: round(x * 1e3, 3)
+    return {"ms_per_trace": ms(dt), "ms_min_max": [ms(dmin), ms(dmax)], "key_switches": nks,
+            "ks_per_s": round(nks / dt, 1), "L_start": spec.L_max, "L_end": Lf, "runs": runs,
+            "graph_ms_per_trace": ms(gdt), "graph_ms_min_max": [ms(gmin), ms(gmax)],
+            "graph_ks_per_s": round(nks / gdt, 1), "graph_equals_eager": same}
 
 
 def serve_numbers(n_requests, budget_gib, sweep_budgets):
